@@ -1,0 +1,170 @@
+/*
+ * gol.h -- C ABI of the MI355X Game-of-Life step library (libgol.so).
+ *
+ * The operation: Conway's Life, rule B3/S23 (the paper, Section 1: every cell
+ * has eight neighbours -- horizontal, vertical and diagonal; all cells change
+ * at once each time step; a live cell with two or three live neighbours
+ * lives on, any other live cell dies; a dead cell with exactly three live
+ * neighbours becomes live) on a torus whose left/right and top/bottom edges
+ * are adjacent (Section 2.2).  A run is fixed by its initial board and its
+ * number of generations (Section 1: the evolution depends on the initial
+ * state only).  Neighbour coordinates wrap modulo the board's sides; on tori
+ * with fewer than 3 rows or columns an offset that lands on a cell already
+ * counted, or on the cell itself, counts again.
+ *
+ * Layouts
+ *   byte board   : rows * cols uint8, row-major; nonzero = alive on input,
+ *                  results are 0 / 1.
+ *   packed board : rows * W uint64 words, W = ceil(cols / 64); cell (r, c) is
+ *                  bit (c mod 64) of word r * W + c / 64, LSB first.  Padding
+ *                  bits (columns >= cols) are ignored on input and written 0.
+ *
+ * Sizes: 1 <= rows, cols <= 2^30, rows * W * 8 bytes must fit the device;
+ * generations >= 0 (0 copies the normalised input).
+ *
+ * Errors: every call returns GOL_OK (0) or a negative code; gol_last_error()
+ * returns a description of the calling thread's last failure.  No C++
+ * exception crosses this interface.
+ *
+ * Streams: `stream` arguments are hipStream_t handles passed as void*
+ * (NULL = the legacy default stream).  Asynchronous calls return once their
+ * work is queued; their buffers must stay valid until it has run.
+ */
+#ifndef GOL_H
+#define GOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GOL_OK = 0,
+  GOL_EINVAL = -1,     /* null pointer, size out of range, generations < 0, bad overlap */
+  GOL_ENOMEM = -2,     /* device or host allocation failed, or request > server budget */
+  GOL_EDEVICE = -3,    /* a HIP call failed; the message names it */
+  GOL_EAGAIN = -4,     /* served request not finished yet */
+  GOL_ENOTFOUND = -5,  /* unknown or already retired ticket */
+  GOL_ECANCELED = -6   /* served request was cancelled */
+};
+
+/* Description of the calling thread's last error ("" if none). */
+const char* gol_last_error(void);
+
+/* Library version string. */
+const char* gol_version(void);
+
+/*
+ * Advance a board held in HOST memory by `generations` generations.
+ * board, out: host byte boards of rows * cols bytes (out == board allowed;
+ * partial overlap -> GOL_EINVAL).  Synchronous: copies the board to the
+ * current HIP device, packs it, runs the tile passes, unpacks and copies
+ * back before returning.
+ */
+int gol_step(const uint8_t* board, int64_t rows, int64_t cols, int64_t generations,
+             uint8_t* out);
+
+/*
+ * Advance a packed board held in DEVICE memory.  d_in, d_out: device
+ * pointers to rows * W words (d_out == d_in allowed; partial overlap ->
+ * GOL_EINVAL).  Asynchronous on `stream`.  The library takes its ping-pong
+ * scratch (one board, two when d_out == d_in and the pass count is odd) from
+ * the device's stream-ordered memory pool, or from the allocator installed
+ * with gol_set_allocator.  `t_block` = generations per pass (the temporal
+ * block): 0 picks the tuned default, else one of 1, 2, 4, 8, 16.
+ */
+int gol_step_packed(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t generations,
+                    uint64_t* d_out, void* stream);
+int gol_step_packed_ex(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t generations,
+                       uint64_t* d_out, void* stream, int t_block);
+
+/* Device conversions between the byte and packed layouts (asynchronous). */
+int gol_pack(const uint8_t* d_bytes, int64_t rows, int64_t cols, uint64_t* d_packed,
+             void* stream);
+int gol_unpack(const uint64_t* d_packed, int64_t rows, int64_t cols, uint8_t* d_bytes,
+               void* stream);
+
+/*
+ * Many independent boards, each with its own size and generation count, in
+ * one schedule of tile passes (uneven sizes share waves; boards that need
+ * more generations keep running while finished ones drop out).
+ * d_in / d_out follow gol_step_packed's rules per board.  Asynchronous.
+ */
+typedef struct {
+  const uint64_t* d_in;
+  uint64_t* d_out;
+  int64_t rows;
+  int64_t cols;
+  int64_t generations;
+} gol_board;
+
+int gol_batch_run(const gol_board* boards, int64_t n, void* stream);
+
+/*
+ * A batch plan: the schedule of gol_batch_run built once and run many times
+ * on the same buffers (the launch sequence is captured into a HIP graph on
+ * the first run and replayed afterwards).  The plan owns its scratch.
+ */
+typedef struct gol_plan gol_plan;
+int gol_plan_create(const gol_board* boards, int64_t n, int t_block, gol_plan** out);
+int gol_plan_run(gol_plan* plan, void* stream);
+/* Describes the plan: waves per level 0, levels, total cell updates. */
+int gol_plan_info(const gol_plan* plan, int64_t* waves, int64_t* levels, double* cell_updates);
+int gol_plan_destroy(gol_plan* plan);
+
+/*
+ * Serving: a request loop with continuous batching.  Requests are admitted
+ * while the boards resident on the device fit `hbm_budget_bytes` (two packed
+ * buffers per board); every tick advances all resident boards by up to
+ * `chunk_generations` in one batched schedule, new arrivals join at the next
+ * tick, finished boards are copied back and leave.
+ */
+typedef struct {
+  uint64_t hbm_budget_bytes;   /* device bytes for resident boards */
+  int32_t chunk_generations;   /* generations per tick (>= 1) */
+  int32_t device;              /* HIP device ordinal */
+  int32_t max_resident;        /* cap on resident boards (0 = no cap) */
+  int32_t t_block;             /* generations per pass, 0 = default */
+} gol_serve_config;
+
+typedef struct gol_server gol_server;
+
+typedef struct {
+  int64_t generations_done;
+  double submit_s;   /* seconds on the server's clock */
+  double admit_s;
+  double done_s;
+} gol_request_info;
+
+int gol_serve_create(const gol_serve_config* cfg, gol_server** out);
+/* Copies rows * W words from host memory before returning. */
+int gol_serve_submit(gol_server* srv, const uint64_t* host_packed, int64_t rows, int64_t cols,
+                     int64_t generations, uint64_t* ticket);
+/* GOL_EAGAIN until done; then writes rows * W words to host_out, fills info
+ * (may be NULL) and retires the ticket. */
+int gol_serve_poll(gol_server* srv, uint64_t ticket, uint64_t* host_out, gol_request_info* info);
+/* Blocks until the ticket is done (or failed / cancelled), then as poll. */
+int gol_serve_wait(gol_server* srv, uint64_t ticket, uint64_t* host_out, gol_request_info* info);
+int gol_serve_cancel(gol_server* srv, uint64_t ticket);
+/* Seconds on the server's clock (the time base of gol_request_info). */
+double gol_serve_now(const gol_server* srv);
+int gol_serve_destroy(gol_server* srv);
+
+/*
+ * Optional allocator for the library's device scratch (e.g. a framework's
+ * caching allocator).  alloc(bytes, stream, ctx) returns device memory usable
+ * in stream order on `stream`; free(ptr, stream, ctx) releases it after the
+ * stream's queued work.  Pass NULLs to restore the default
+ * (hipMallocAsync / hipFreeAsync).
+ */
+typedef void* (*gol_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*gol_free_fn)(void* ptr, void* stream, void* ctx);
+int gol_set_allocator(gol_alloc_fn alloc, gol_free_fn free_fn, void* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GOL_H */

@@ -1,0 +1,309 @@
+"""Python binding of libgol (the C ABI in include/gol.h): argument marshalling only.
+
+Every step of the Life computation runs in the library's HIP kernels; torch
+only supplies device memory (packed boards are int64 tensors of shape
+(rows, ceil(cols / 64)), reinterpreted as uint64 words) and HIP streams.
+If libgol.so is missing this module raises on first use: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgol.so")
+
+GOL_OK = 0
+GOL_EINVAL = -1
+GOL_ENOMEM = -2
+GOL_EDEVICE = -3
+GOL_EAGAIN = -4
+GOL_ENOTFOUND = -5
+GOL_ECANCELED = -6
+
+_lib = None
+
+
+class GolError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Board(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_void_p), ("d_out", ctypes.c_void_p), ("rows", ctypes.c_int64),
+                ("cols", ctypes.c_int64), ("generations", ctypes.c_int64)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("chunk_generations", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("max_resident", ctypes.c_int32),
+                ("t_block", ctypes.c_int32)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("generations_done", ctypes.c_int64), ("submit_s", ctypes.c_double),
+                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
+def lib():
+    """Load libgol.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+        sig = {
+            "gol_last_error": (ctypes.c_char_p, []),
+            "gol_version": (ctypes.c_char_p, []),
+            "gol_step": (c_int, [vp, i64, i64, i64, vp]),
+            "gol_step_packed": (c_int, [vp, i64, i64, i64, vp, vp]),
+            "gol_step_packed_ex": (c_int, [vp, i64, i64, i64, vp, vp, c_int]),
+            "gol_pack": (c_int, [vp, i64, i64, vp, vp]),
+            "gol_unpack": (c_int, [vp, i64, i64, vp, vp]),
+            "gol_batch_run": (c_int, [vp, i64, vp]),
+            "gol_plan_create": (c_int, [vp, i64, c_int, ctypes.POINTER(vp)]),
+            "gol_plan_run": (c_int, [vp, vp]),
+            "gol_plan_info": (c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                      ctypes.POINTER(ctypes.c_double)]),
+            "gol_plan_destroy": (c_int, [vp]),
+            "gol_serve_create": (c_int, [ctypes.POINTER(ServeConfig), ctypes.POINTER(vp)]),
+            "gol_serve_submit": (c_int, [vp, vp, i64, i64, i64, ctypes.POINTER(ctypes.c_uint64)]),
+            "gol_serve_poll": (c_int, [vp, ctypes.c_uint64, vp, ctypes.POINTER(RequestInfo)]),
+            "gol_serve_wait": (c_int, [vp, ctypes.c_uint64, vp, ctypes.POINTER(RequestInfo)]),
+            "gol_serve_cancel": (c_int, [vp, ctypes.c_uint64]),
+            "gol_serve_now": (ctypes.c_double, [vp]),
+            "gol_serve_destroy": (c_int, [vp]),
+            "gol_set_allocator": (c_int, [vp, vp, vp]),
+            "gol_debug_plan_tables": (c_int, [vp, vp, vp, i64, c_int, c_int, vp, i64, vp, i64, vp,
+                                              i64, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                              ctypes.POINTER(i64)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc != GOL_OK:
+        raise GolError(rc, lib().gol_last_error().decode(errors="replace"))
+    return rc
+
+
+def version() -> str:
+    return lib().gol_version().decode()
+
+
+def words_per_row(cols: int) -> int:
+    return (int(cols) + 63) // 64
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# Single board
+# ---------------------------------------------------------------------------
+def step(board: np.ndarray, generations: int, out: Optional[np.ndarray] = None) -> np.ndarray:
+    """Host byte board (rows, cols), nonzero = alive -> 0/1 uint8 after G generations."""
+    b = np.ascontiguousarray(board, dtype=np.uint8)
+    if b.ndim != 2:
+        raise ValueError("board must be 2-D")
+    if out is None:
+        out = np.empty_like(b)
+    rows, cols = b.shape
+    _check(lib().gol_step(b.ctypes.data, rows, cols, int(generations), out.ctypes.data))
+    return out
+
+
+def empty_packed(rows: int, cols: int, device="cuda"):
+    import torch
+    return torch.empty((rows, words_per_row(cols)), dtype=torch.int64, device=device)
+
+
+def step_packed(d_in, rows: int, cols: int, generations: int, d_out=None, stream=None,
+                t_block: int = 0):
+    """Packed device board -> packed device board (asynchronous on `stream`)."""
+    if d_out is None:
+        d_out = empty_packed(rows, cols, d_in.device)
+    _check(lib().gol_step_packed_ex(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
+                                    _stream_handle(stream), int(t_block)))
+    return d_out
+
+
+def pack(d_bytes, rows: int, cols: int, d_out=None, stream=None):
+    if d_out is None:
+        d_out = empty_packed(rows, cols, d_bytes.device)
+    _check(lib().gol_pack(_ptr(d_bytes), rows, cols, _ptr(d_out), _stream_handle(stream)))
+    return d_out
+
+
+def unpack(d_packed, rows: int, cols: int, d_out=None, stream=None):
+    import torch
+    if d_out is None:
+        d_out = torch.empty((rows, cols), dtype=torch.uint8, device=d_packed.device)
+    _check(lib().gol_unpack(_ptr(d_packed), rows, cols, _ptr(d_out), _stream_handle(stream)))
+    return d_out
+
+
+# ---------------------------------------------------------------------------
+# Many boards
+# ---------------------------------------------------------------------------
+@dataclass
+class BatchBoard:
+    d_in: object
+    d_out: object
+    rows: int
+    cols: int
+    generations: int
+
+
+def _board_array(boards: Sequence[BatchBoard]):
+    arr = (Board * max(1, len(boards)))()
+    for i, b in enumerate(boards):
+        arr[i] = Board(_ptr(b.d_in), _ptr(b.d_out), b.rows, b.cols, b.generations)
+    return arr
+
+
+def batch_run(boards: Sequence[BatchBoard], stream=None) -> None:
+    arr = _board_array(boards)
+    _check(lib().gol_batch_run(ctypes.cast(arr, ctypes.c_void_p), len(boards),
+                               _stream_handle(stream)))
+
+
+class Plan:
+    """A batch schedule built once and replayed (HIP graph) on the same buffers."""
+
+    def __init__(self, boards: Sequence[BatchBoard], t_block: int = 0):
+        self._boards = list(boards)  # keep the tensors alive
+        arr = _board_array(self._boards)
+        h = ctypes.c_void_p()
+        _check(lib().gol_plan_create(ctypes.cast(arr, ctypes.c_void_p), len(self._boards),
+                                     int(t_block), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None) -> None:
+        _check(lib().gol_plan_run(self._h, _stream_handle(stream)))
+
+    def info(self):
+        w, lv, cu = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        _check(lib().gol_plan_info(self._h, ctypes.byref(w), ctypes.byref(lv), ctypes.byref(cu)))
+        return {"waves_level0": w.value, "levels": lv.value, "cell_updates": cu.value}
+
+    def close(self) -> None:
+        if self._h:
+            lib().gol_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+class Server:
+    """Continuous-batching request loop (gol_serve_*)."""
+
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, chunk_generations: int = 64,
+                 device: int = 0, max_resident: int = 0, t_block: int = 0):
+        cfg = ServeConfig(hbm_budget_bytes, chunk_generations, device, max_resident, t_block)
+        h = ctypes.c_void_p()
+        _check(lib().gol_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, packed: np.ndarray, rows: int, cols: int, generations: int) -> int:
+        a = np.ascontiguousarray(packed).view(np.uint64)
+        if a.size != rows * words_per_row(cols):
+            raise ValueError("packed board has the wrong size")
+        t = ctypes.c_uint64()
+        _check(lib().gol_serve_submit(self._h, a.ctypes.data, rows, cols, int(generations),
+                                      ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, out: np.ndarray):
+        info = RequestInfo()
+        rc = lib().gol_serve_poll(self._h, ticket, out.ctypes.data, ctypes.byref(info))
+        if rc == GOL_EAGAIN:
+            return None
+        _check(rc)
+        return info
+
+    def wait(self, ticket: int, out: np.ndarray) -> RequestInfo:
+        info = RequestInfo()
+        _check(lib().gol_serve_wait(self._h, ticket, out.ctypes.data, ctypes.byref(info)))
+        return info
+
+    def cancel(self, ticket: int) -> None:
+        _check(lib().gol_serve_cancel(self._h, ticket))
+
+    def now(self) -> float:
+        return float(lib().gol_serve_now(self._h))
+
+    def close(self) -> None:
+        if self._h:
+            lib().gol_serve_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# Host-only view of the batch planner (no device work)
+# ---------------------------------------------------------------------------
+SEGMENT_DTYPE = np.dtype([("board", "<i4"), ("p0", "<i4"), ("r0", "<i4"), ("h", "<u2"),
+                          ("lane0", "u1"), ("nlanes", "u1")])
+WAVEITEM_DTYPE = np.dtype([("seg_begin", "<i4"), ("nseg", "<i2"), ("h", "<u2"), ("maxK", "<i4"),
+                           ("flags", "<i4")])
+
+
+def plan_tables(rows: Iterable[int], cols: Iterable[int], generations: Iterable[int],
+                t_block: int = 8, band_rows: int = 64):
+    r = np.ascontiguousarray(list(rows), dtype=np.int64)
+    c = np.ascontiguousarray(list(cols), dtype=np.int64)
+    g = np.ascontiguousarray(list(generations), dtype=np.int64)
+    ns, ni, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().gol_debug_plan_tables(r.ctypes.data, c.ctypes.data, g.ctypes.data, len(r),
+                                       t_block, band_rows, None, 0, None, 0, None, 0,
+                                       ctypes.byref(ns), ctypes.byref(ni), ctypes.byref(nl)))
+    segs = np.zeros(ns.value, dtype=SEGMENT_DTYPE)
+    items = np.zeros(ni.value, dtype=WAVEITEM_DTYPE)
+    levels = np.zeros(nl.value, dtype=np.int32)
+    _check(lib().gol_debug_plan_tables(r.ctypes.data, c.ctypes.data, g.ctypes.data, len(r),
+                                       t_block, band_rows, segs.ctypes.data, len(segs),
+                                       items.ctypes.data, len(items), levels.ctypes.data,
+                                       len(levels), ctypes.byref(ns), ctypes.byref(ni),
+                                       ctypes.byref(nl)))
+    return segs, items, levels

@@ -1,0 +1,54 @@
+"""Build libgol.so (HIP kernels for gfx950 + the C ABI) in-tree with hipcc."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(PKG, "libgol.so")
+OBJ = os.path.join(PKG, "_build")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall",
+          "-Wno-unused-function"]
+# Device code: gfx950 only; keep the compiler from forming packed-FP32 ops.
+DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-munsafe-fp-atomics"]
+HOST_SOURCES = ["gol_capi.cpp", "gol_plan.cpp", "gol_serve.cpp"]
+DEVICE_SOURCES = ["gol_kernels.hip"]
+
+
+def _run(cmd: list[str]) -> None:
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("build step failed: " + " ".join(cmd))
+
+
+def build(save_temps: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    objs = []
+    for s in DEVICE_SOURCES:
+        o = os.path.join(OBJ, s + ".o")
+        cmd = [HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, s), "-o", o]
+        if save_temps:
+            cmd += ["-save-temps=obj"]
+        _run(cmd)
+        objs.append(o)
+    for s in HOST_SOURCES:
+        o = os.path.join(OBJ, s + ".o")
+        _run([HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, s), "-o", o])
+        objs.append(o)
+    tmp = LIB + ".tmp"
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(save_temps="--save-temps" in sys.argv))

@@ -1,0 +1,647 @@
+// C ABI of libgol: argument checks, device scratch, pass sequencing, batch
+// plans.  Declared in include/gol.h.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gol.h"
+#include "gol_debug.h"
+#include "gol_internal.h"
+#include "gol_plan.h"
+#include "gol_runtime.h"
+
+namespace gol {
+
+// Launchers defined in gol_kernels.hip.
+hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
+                             int32_t D, const GridGeom& g, hipStream_t st);
+hipError_t launch_batch_pass(int T, bool masked, const BoardDesc* boards, const Segment* segs,
+                             const WaveItem* items, int nitems, int level, hipStream_t st);
+hipError_t launch_pack(const uint8_t* in, int64_t R, int64_t C, uint64_t* out, hipStream_t st);
+hipError_t launch_unpack(const uint64_t* in, int64_t R, int64_t C, uint8_t* out, hipStream_t st);
+hipError_t launch_copy_clear_padding(const uint64_t* in, int64_t R, int64_t C, uint64_t* out,
+                                     hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local std::string t_last_error;
+
+int set_error(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  t_last_error = buf;
+  return code;
+}
+
+int hip_error(hipError_t e, const char* what) {
+  return set_error(GOL_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { t_last_error.clear(); }
+
+const char* last_error() { return t_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// Device scratch allocation (stream ordered)
+// ---------------------------------------------------------------------------
+static std::mutex g_alloc_mu;
+static gol_alloc_fn g_alloc = nullptr;
+static gol_free_fn g_free = nullptr;
+static void* g_alloc_ctx = nullptr;
+static std::vector<int> g_pool_ready;
+
+static void ensure_pool(int dev) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  if ((int)g_pool_ready.size() <= dev) g_pool_ready.resize(dev + 1, 0);
+  if (g_pool_ready[dev]) return;
+  hipMemPool_t pool;
+  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+    uint64_t thr = UINT64_MAX;  // keep freed blocks cached in the pool
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+  }
+  g_pool_ready[dev] = 1;
+}
+
+int scratch_alloc(void** p, size_t bytes, hipStream_t st) {
+  gol_alloc_fn a;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    a = g_alloc;
+    ctx = g_alloc_ctx;
+  }
+  if (bytes == 0) bytes = 256;
+  if (a) {
+    *p = a(bytes, (void*)st, ctx);
+    if (!*p) return set_error(GOL_ENOMEM, "installed allocator returned NULL for %zu bytes", bytes);
+    return GOL_OK;
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  ensure_pool(dev);
+  e = hipMallocAsync(p, bytes, st);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(GOL_ENOMEM, "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
+  }
+  return GOL_OK;
+}
+
+void scratch_free(void* p, hipStream_t st) {
+  if (!p) return;
+  gol_free_fn f;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    f = g_free;
+    ctx = g_alloc_ctx;
+  }
+  if (f)
+    f(p, (void*)st, ctx);
+  else
+    (void)hipFreeAsync(p, st);
+}
+
+// Pinned host staging that must outlive queued copies: freed once the event
+// recorded after its last use has completed.
+static std::mutex g_defer_mu;
+static std::vector<std::pair<hipEvent_t, void*>> g_deferred;
+
+void reap_deferred(bool wait) {
+  std::lock_guard<std::mutex> lk(g_defer_mu);
+  size_t k = 0;
+  for (auto& d : g_deferred) {
+    if (wait) (void)hipEventSynchronize(d.first);
+    if (hipEventQuery(d.first) == hipSuccess) {
+      (void)hipEventDestroy(d.first);
+      (void)hipHostFree(d.second);
+    } else {
+      g_deferred[k++] = d;
+    }
+  }
+  g_deferred.resize(k);
+}
+
+int defer_host_free(void* pinned, hipStream_t st) {
+  hipEvent_t ev;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev, st);
+  if (e != hipSuccess) return hip_error(e, "hipEventRecord");
+  std::lock_guard<std::mutex> lk(g_defer_mu);
+  g_deferred.emplace_back(ev, pinned);
+  return GOL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Checks
+// ---------------------------------------------------------------------------
+int check_board(int64_t rows, int64_t cols, int64_t gens) {
+  if (rows < 1 || cols < 1 || rows > (1 << 30) || cols > (1 << 30))
+    return set_error(GOL_EINVAL, "rows and cols must be in [1, 2^30] (got %lld x %lld)",
+                     (long long)rows, (long long)cols);
+  if (gens < 0) return set_error(GOL_EINVAL, "generations must be >= 0 (got %lld)", (long long)gens);
+  const int64_t W = (cols + 63) / 64;
+  if (rows > INT64_MAX / 8 / W) return set_error(GOL_EINVAL, "board too large");
+  return GOL_OK;
+}
+
+bool ranges_partially_overlap(const void* a, const void* b, size_t bytes) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  if (x == y) return false;
+  return x < y + bytes && y < x + bytes;
+}
+
+int default_T() { return 8; }
+
+// ---------------------------------------------------------------------------
+// Single board
+// ---------------------------------------------------------------------------
+int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t* d_out,
+                hipStream_t st, int T, int band_rows) {
+  int rc = check_board(R, C, G);
+  if (rc) return rc;
+  if (!d_in || !d_out) return set_error(GOL_EINVAL, "null board pointer");
+  if (T == 0) T = default_T();
+  if (!valid_T(T)) return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8 or 16 (got %d)", T);
+  const int64_t W = (C + 63) / 64, D = 2 * W;
+  const size_t bytes = (size_t)(R * W * 8);
+  if (ranges_partially_overlap(d_in, d_out, bytes))
+    return set_error(GOL_EINVAL, "d_in and d_out partially overlap");
+  reap_deferred(false);
+  if (G == 0) {
+    hipError_t e = launch_copy_clear_padding(d_in, R, C, d_out, st);
+    return e == hipSuccess ? GOL_OK : hip_error(e, "copy kernel launch");
+  }
+  const std::vector<int> passes = single_board_passes(G, T);
+  const int K = (int)passes.size();
+  void* s1v = nullptr;
+  rc = scratch_alloc(&s1v, bytes, st);
+  if (rc) return rc;
+  uint32_t* s1 = (uint32_t*)s1v;
+  uint32_t* out = (uint32_t*)d_out;
+  const uint32_t* src0 = (const uint32_t*)d_in;
+  uint32_t* w[2] = {out, s1};
+  int par = (K - 1) & 1;
+  hipError_t e = hipSuccess;
+  if ((const void*)d_in == (const void*)d_out && (K & 1)) {
+    // pass 0 must not write the board it reads: start from a copy
+    e = launch_copy_clear_padding(d_in, R, C, (uint64_t*)s1, st);
+    src0 = s1;
+    par = 0;
+  }
+  for (int j = 0; j < K && e == hipSuccess; ++j) {
+    const uint32_t* src = (j == 0) ? src0 : w[(j - 1 + par) & 1];
+    uint32_t* dst = w[(j + par) & 1];
+    const int Tj = passes[j];
+    const int br = band_rows > 0 ? band_rows : default_band_rows(R, C, Tj);
+    const GridGeom g = board_geometry(R, C, br);
+    e = launch_board_pass(Tj, src, dst, (int32_t)R, (int32_t)C, (int32_t)D, g, st);
+  }
+  scratch_free(s1v, st);
+  if (e != hipSuccess) return hip_error(e, "tile pass launch");
+  return GOL_OK;
+}
+
+// Library streams for the synchronous host API.
+static std::mutex g_stream_mu;
+static std::vector<hipStream_t> g_streams;
+
+static int acquire_stream(hipStream_t* st) {
+  {
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    if (!g_streams.empty()) {
+      *st = g_streams.back();
+      g_streams.pop_back();
+      return GOL_OK;
+    }
+  }
+  hipError_t e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+  return e == hipSuccess ? GOL_OK : hip_error(e, "hipStreamCreate");
+}
+
+static void release_stream(hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_stream_mu);
+  g_streams.push_back(st);
+}
+
+int step_host(const uint8_t* board, int64_t R, int64_t C, int64_t G, uint8_t* out, int T) {
+  int rc = check_board(R, C, G);
+  if (rc) return rc;
+  if (!board || !out) return set_error(GOL_EINVAL, "null board pointer");
+  if (R > INT64_MAX / C) return set_error(GOL_EINVAL, "board too large");
+  const size_t N = (size_t)(R * C);
+  if (ranges_partially_overlap(board, out, N))
+    return set_error(GOL_EINVAL, "board and out partially overlap");
+  const int64_t W = (C + 63) / 64;
+  const size_t words_bytes = (size_t)(R * W * 8);
+  hipStream_t st;
+  rc = acquire_stream(&st);
+  if (rc) return rc;
+  void *db = nullptr, *pa = nullptr, *pb = nullptr;
+  rc = scratch_alloc(&db, N, st);
+  if (!rc) rc = scratch_alloc(&pa, words_bytes, st);
+  if (!rc) rc = scratch_alloc(&pb, words_bytes, st);
+  hipError_t e = hipSuccess;
+  if (!rc) {
+    e = hipMemcpyAsync(db, board, N, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_pack((const uint8_t*)db, R, C, (uint64_t*)pa, st);
+    if (e == hipSuccess) {
+      rc = step_packed((const uint64_t*)pa, R, C, G, (uint64_t*)pb, st, T, 0);
+      if (!rc) {
+        e = launch_unpack((const uint64_t*)pb, R, C, (uint8_t*)db, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(out, db, N, hipMemcpyDeviceToHost, st);
+      }
+    }
+  }
+  scratch_free(pb, st);
+  scratch_free(pa, st);
+  scratch_free(db, st);
+  hipError_t e2 = hipStreamSynchronize(st);
+  release_stream(st);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_error(e, "gol_step");
+  if (e2 != hipSuccess) return hip_error(e2, "hipStreamSynchronize");
+  return GOL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batch plans
+// ---------------------------------------------------------------------------
+
+
+// Validates, plans and fills the board descriptors given a scratch base.
+int plan_boards(const gol_board* boards, int64_t n, int T, int band_rows, DevicePlan& P) {
+  if (n < 0 || (n > 0 && !boards)) return set_error(GOL_EINVAL, "bad board array");
+  if (n > (int64_t)1 << 24) return set_error(GOL_EINVAL, "too many boards");
+  if (T == 0) T = default_T();
+  if (!valid_T(T)) return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8 or 16 (got %d)", T);
+  std::vector<BoardReq> req((size_t)n);
+  P.boards.assign(boards, boards + n);
+  P.scratch_off.assign((size_t)n, 0);
+  size_t off = 0;
+  for (int64_t b = 0; b < n; ++b) {
+    const gol_board& g = boards[b];
+    int rc = check_board(g.rows, g.cols, g.generations);
+    if (rc) return set_error(rc, "board %lld: %s", (long long)b, last_error());
+    if (!g.d_in || !g.d_out) return set_error(GOL_EINVAL, "board %lld: null pointer", (long long)b);
+    const int64_t W = (g.cols + 63) / 64;
+    if (ranges_partially_overlap(g.d_in, g.d_out, (size_t)(g.rows * W * 8)))
+      return set_error(GOL_EINVAL, "board %lld: d_in and d_out partially overlap", (long long)b);
+    req[b] = BoardReq{g.rows, g.cols, g.generations};
+    if (g.generations > 0) {
+      P.scratch_off[b] = off;
+      off += (size_t)(g.rows * W);
+    }
+  }
+  P.scratch_words = off;
+  std::string err;
+  if (!build_plan(req, T, band_rows > 0 ? band_rows : 64, P.hp, err))
+    return set_error(GOL_EINVAL, "%s", err.c_str());
+  return GOL_OK;
+}
+
+void fill_board_descs(DevicePlan& P) {
+  const size_t n = P.boards.size();
+  P.h_boards.assign(n, BoardDesc{});
+  P.copy_first.clear();
+  P.zero_gen.clear();
+  for (size_t b = 0; b < n; ++b) {
+    const gol_board& g = P.boards[b];
+    BoardDesc& d = P.h_boards[b];
+    const int64_t W = (g.cols + 63) / 64;
+    d.R = (int32_t)g.rows;
+    d.C = (int32_t)g.cols;
+    d.D = (int32_t)(2 * W);
+    d.K = P.hp.K[b];
+    d.Tfirst = P.hp.Tfirst[b];
+    if (d.K == 0) {
+      P.zero_gen.push_back((int)b);
+      d.src0 = (const uint32_t*)g.d_in;
+      d.w[0] = d.w[1] = (uint32_t*)g.d_out;
+      continue;
+    }
+    uint32_t* s1 = (uint32_t*)(P.d_scratch + P.scratch_off[b]);
+    d.w[0] = (uint32_t*)g.d_out;
+    d.w[1] = s1;
+    d.src0 = (const uint32_t*)g.d_in;
+    d.par = (d.K - 1) & 1;
+    if ((const void*)g.d_in == (const void*)g.d_out && (d.K & 1)) {
+      P.copy_first.push_back((int)b);
+      d.src0 = s1;
+      d.par = 0;
+    }
+  }
+}
+
+hipError_t enqueue_plan(const DevicePlan& P, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int b : P.zero_gen) {
+    const gol_board& g = P.boards[b];
+    e = launch_copy_clear_padding(g.d_in, g.rows, g.cols, g.d_out, st);
+    if (e != hipSuccess) return e;
+  }
+  for (int b : P.copy_first) {
+    const gol_board& g = P.boards[b];
+    e = launch_copy_clear_padding(g.d_in, g.rows, g.cols, P.d_scratch + P.scratch_off[b], st);
+    if (e != hipSuccess) return e;
+  }
+  for (size_t L = 0; L < P.hp.level_items.size(); ++L) {
+    e = launch_batch_pass(P.hp.T, L == 0 && P.hp.level0_masked, P.d_boards, P.d_segs, P.d_items,
+                          P.hp.level_items[L], (int)L, st);
+    if (e != hipSuccess) return e;
+  }
+  return e;
+}
+
+// Uploads boards / segments / items into one device block at `dev`.
+static size_t meta_bytes(const DevicePlan& P, size_t* ob, size_t* os, size_t* oi) {
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  *ob = 0;
+  *os = al(P.h_boards.size() * sizeof(BoardDesc));
+  *oi = *os + al(P.hp.segs.size() * sizeof(Segment));
+  return *oi + al(P.hp.items.size() * sizeof(WaveItem));
+}
+
+static void fill_meta_host(const DevicePlan& P, char* host, size_t ob, size_t os, size_t oi) {
+  memcpy(host + ob, P.h_boards.data(), P.h_boards.size() * sizeof(BoardDesc));
+  memcpy(host + os, P.hp.segs.data(), P.hp.segs.size() * sizeof(Segment));
+  memcpy(host + oi, P.hp.items.data(), P.hp.items.size() * sizeof(WaveItem));
+}
+
+int batch_run(const gol_board* boards, int64_t n, hipStream_t st, int T) {
+  reap_deferred(false);
+  DevicePlan P;
+  int rc = plan_boards(boards, n, T, 0, P);
+  if (rc) return rc;
+  if (n == 0) return GOL_OK;
+  void* scratch = nullptr;
+  void* meta = nullptr;
+  if (P.scratch_words) {
+    rc = scratch_alloc(&scratch, P.scratch_words * 8, st);
+    if (rc) return rc;
+  }
+  P.d_scratch = (uint64_t*)scratch;
+  fill_board_descs(P);
+  size_t ob, os, oi;
+  const size_t mb = meta_bytes(P, &ob, &os, &oi);
+  rc = scratch_alloc(&meta, mb, st);
+  if (rc) {
+    scratch_free(scratch, st);
+    return rc;
+  }
+  void* pinned = nullptr;
+  hipError_t e = hipHostMalloc(&pinned, mb, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    scratch_free(meta, st);
+    scratch_free(scratch, st);
+    return set_error(GOL_ENOMEM, "hipHostMalloc(%zu): %s", mb, hipGetErrorString(e));
+  }
+  fill_meta_host(P, (char*)pinned, ob, os, oi);
+  e = hipMemcpyAsync(meta, pinned, mb, hipMemcpyHostToDevice, st);
+  P.d_boards = (BoardDesc*)((char*)meta + ob);
+  P.d_segs = (Segment*)((char*)meta + os);
+  P.d_items = (WaveItem*)((char*)meta + oi);
+  if (e == hipSuccess) e = enqueue_plan(P, st);
+  scratch_free(meta, st);
+  scratch_free(scratch, st);
+  rc = defer_host_free(pinned, st);
+  if (e != hipSuccess) return hip_error(e, "gol_batch_run");
+  return rc;
+}
+
+}  // namespace gol
+
+// ---------------------------------------------------------------------------
+// extern "C"
+// ---------------------------------------------------------------------------
+using namespace gol;
+
+struct gol_plan {
+  DevicePlan P;
+  void* meta = nullptr;
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+const char* gol_last_error(void) { return gol::last_error(); }
+
+const char* gol_version(void) { return "golmi 0.1 (gfx950)"; }
+
+int gol_step(const uint8_t* board, int64_t rows, int64_t cols, int64_t generations, uint8_t* out) {
+  try {
+    return step_host(board, rows, cols, generations, out, 0);
+  } catch (const std::bad_alloc&) {
+    return set_error(GOL_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(GOL_EDEVICE, "unexpected exception");
+  }
+}
+
+int gol_step_packed_ex(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t generations,
+                       uint64_t* d_out, void* stream, int t_block) {
+  try {
+    return step_packed(d_in, rows, cols, generations, d_out, (hipStream_t)stream, t_block, 0);
+  } catch (const std::bad_alloc&) {
+    return set_error(GOL_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(GOL_EDEVICE, "unexpected exception");
+  }
+}
+
+int gol_step_packed(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t generations,
+                    uint64_t* d_out, void* stream) {
+  return gol_step_packed_ex(d_in, rows, cols, generations, d_out, stream, 0);
+}
+
+int gol_pack(const uint8_t* d_bytes, int64_t rows, int64_t cols, uint64_t* d_packed,
+             void* stream) {
+  int rc = check_board(rows, cols, 0);
+  if (rc) return rc;
+  if (!d_bytes || !d_packed) return set_error(GOL_EINVAL, "null pointer");
+  hipError_t e = launch_pack(d_bytes, rows, cols, d_packed, (hipStream_t)stream);
+  return e == hipSuccess ? GOL_OK : hip_error(e, "pack kernel launch");
+}
+
+int gol_unpack(const uint64_t* d_packed, int64_t rows, int64_t cols, uint8_t* d_bytes,
+               void* stream) {
+  int rc = check_board(rows, cols, 0);
+  if (rc) return rc;
+  if (!d_bytes || !d_packed) return set_error(GOL_EINVAL, "null pointer");
+  hipError_t e = launch_unpack(d_packed, rows, cols, d_bytes, (hipStream_t)stream);
+  return e == hipSuccess ? GOL_OK : hip_error(e, "unpack kernel launch");
+}
+
+int gol_batch_run(const gol_board* boards, int64_t n, void* stream) {
+  try {
+    return batch_run(boards, n, (hipStream_t)stream, 0);
+  } catch (const std::bad_alloc&) {
+    return set_error(GOL_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(GOL_EDEVICE, "unexpected exception");
+  }
+}
+
+int gol_plan_create(const gol_board* boards, int64_t n, int t_block, gol_plan** out) {
+  if (!out) return set_error(GOL_EINVAL, "null output pointer");
+  *out = nullptr;
+  gol_plan* p = nullptr;
+  try {
+    p = new gol_plan();
+    int rc = plan_boards(boards, n, t_block, 0, p->P);
+    if (rc) {
+      delete p;
+      return rc;
+    }
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+      delete p;
+      return hip_error(e, "hipGetDevice");
+    }
+    if (p->P.scratch_words) {
+      e = hipMalloc((void**)&p->P.d_scratch, p->P.scratch_words * 8);
+      if (e != hipSuccess) {
+        delete p;
+        return set_error(GOL_ENOMEM, "hipMalloc scratch (%zu bytes): %s", p->P.scratch_words * 8,
+                         hipGetErrorString(e));
+      }
+    }
+    fill_board_descs(p->P);
+    size_t ob, os, oi;
+    const size_t mb = meta_bytes(p->P, &ob, &os, &oi);
+    e = hipMalloc(&p->meta, mb);
+    if (e != hipSuccess) {
+      (void)hipFree(p->P.d_scratch);
+      delete p;
+      return set_error(GOL_ENOMEM, "hipMalloc plan tables: %s", hipGetErrorString(e));
+    }
+    std::vector<char> host(mb);
+    fill_meta_host(p->P, host.data(), ob, os, oi);
+    e = hipMemcpy(p->meta, host.data(), mb, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(p->meta);
+      (void)hipFree(p->P.d_scratch);
+      delete p;
+      return hip_error(e, "hipMemcpy plan tables");
+    }
+    p->P.d_boards = (BoardDesc*)((char*)p->meta + ob);
+    p->P.d_segs = (Segment*)((char*)p->meta + os);
+    p->P.d_items = (WaveItem*)((char*)p->meta + oi);
+    *out = p;
+    return GOL_OK;
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return set_error(GOL_ENOMEM, "host allocation failed");
+  }
+}
+
+int gol_plan_run(gol_plan* p, void* stream) {
+  if (!p) return set_error(GOL_EINVAL, "null plan");
+  hipStream_t st = (hipStream_t)stream;
+  if (st == nullptr) {
+    hipError_t e = enqueue_plan(p->P, st);
+    return e == hipSuccess ? GOL_OK : hip_error(e, "gol_plan_run");
+  }
+  if (!p->exec) {
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
+    hipError_t el = enqueue_plan(p->P, st);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(st, &g);
+    if (el != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_error(el, "plan launch during capture");
+    }
+    if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      p->exec = nullptr;
+      return hip_error(e, "hipGraphInstantiate");
+    }
+    p->graph = g;
+  }
+  hipError_t e = hipGraphLaunch(p->exec, st);
+  return e == hipSuccess ? GOL_OK : hip_error(e, "hipGraphLaunch");
+}
+
+int gol_plan_info(const gol_plan* p, int64_t* waves, int64_t* levels, double* cell_updates) {
+  if (!p) return set_error(GOL_EINVAL, "null plan");
+  if (waves) *waves = p->P.hp.level_items.empty() ? 0 : p->P.hp.level_items[0];
+  if (levels) *levels = (int64_t)p->P.hp.level_items.size();
+  if (cell_updates) *cell_updates = p->P.hp.cell_updates;
+  return GOL_OK;
+}
+
+int gol_plan_destroy(gol_plan* p) {
+  if (!p) return GOL_OK;
+  (void)hipDeviceSynchronize();
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->meta) (void)hipFree(p->meta);
+  if (p->P.d_scratch) (void)hipFree(p->P.d_scratch);
+  delete p;
+  return GOL_OK;
+}
+
+int gol_set_allocator(gol_alloc_fn alloc, gol_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return set_error(GOL_EINVAL, "alloc and free must both be set or both be NULL");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = alloc;
+  g_free = free_fn;
+  g_alloc_ctx = ctx;
+  return GOL_OK;
+}
+
+// Host-only view of a batch schedule (no device work): used to test the
+// planner.  rows/cols/generations: n entries.  Writes up to cap_segs
+// segments and cap_items waves; returns their counts and the level sizes
+// (up to cap_levels).  Returns GOL_EINVAL on invalid boards.
+int gol_debug_plan_tables(const int64_t* rows, const int64_t* cols, const int64_t* gens, int64_t n,
+                          int t_block, int band_rows, void* segs, int64_t cap_segs, void* items,
+                          int64_t cap_items, int32_t* level_items, int64_t cap_levels,
+                          int64_t* nsegs, int64_t* nitems, int64_t* nlevels) {
+  try {
+    if (n < 0 || (n > 0 && (!rows || !cols || !gens))) return set_error(GOL_EINVAL, "bad arrays");
+    std::vector<BoardReq> req((size_t)n);
+    for (int64_t b = 0; b < n; ++b) req[b] = BoardReq{rows[b], cols[b], gens[b]};
+    HostPlan hp;
+    std::string err;
+    if (t_block == 0) t_block = default_T();
+    if (!build_plan(req, t_block, band_rows > 0 ? band_rows : 64, hp, err))
+      return set_error(GOL_EINVAL, "%s", err.c_str());
+    if (nsegs) *nsegs = (int64_t)hp.segs.size();
+    if (nitems) *nitems = (int64_t)hp.items.size();
+    if (nlevels) *nlevels = (int64_t)hp.level_items.size();
+    if (segs)
+      memcpy(segs, hp.segs.data(),
+             std::min<size_t>(hp.segs.size(), (size_t)cap_segs) * sizeof(Segment));
+    if (items)
+      memcpy(items, hp.items.data(),
+             std::min<size_t>(hp.items.size(), (size_t)cap_items) * sizeof(WaveItem));
+    if (level_items)
+      memcpy(level_items, hp.level_items.data(),
+             std::min<size_t>(hp.level_items.size(), (size_t)cap_levels) * sizeof(int32_t));
+    return GOL_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(GOL_ENOMEM, "host allocation failed");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Internal types shared by the planner (host C++) and the HIP kernels.
+//
+// Board layout in device memory (the library boundary's packed layout): a
+// board of R rows and C columns is R rows of W = ceil(C / 64) uint64 words;
+// cell (r, c) is bit (c mod 64) of word r * W + c / 64, LSB first, and bits at
+// columns >= C are 0.  The kernels read it as 32-bit words: row r holds
+// D = 2 * W dwords, dword j carries cells 32 j .. 32 j + 31 (bit i = cell
+// 32 j + i), because a little-endian uint64 is its low dword then its high one.
+#pragma once
+#include <stdint.h>
+
+namespace gol {
+
+// Upper bound on generations per pass: a halo of one 32-bit word per side is
+// enough while at most 32 generations eat into it, one bit per generation.
+constexpr int kMaxT = 32;
+// Lanes per wave (CDNA wave64).
+constexpr int kWave = 64;
+// Useful columns of a strip that fills a whole wave: 64 lanes minus two halo lanes.
+constexpr int kStripDwords = kWave - 2;
+
+// One board as seen by one launch of the pass kernel.  Pass j (0-based) of
+// the board reads  src0            if j == 0,
+//                  w[(j-1+par)&1]  otherwise,
+// and writes       w[(j+par)&1].
+// Pass 0 advances Tfirst generations, every later pass the kernel's T.
+struct BoardDesc {
+  const uint32_t* src0;
+  uint32_t* w[2];
+  int32_t R;       // rows
+  int32_t C;       // columns (cells per row)
+  int32_t D;       // dwords per row = 2 * ceil(C / 64)
+  int32_t K;       // passes
+  int32_t Tfirst;  // generations of pass 0, 1 <= Tfirst <= T
+  int32_t par;
+};
+
+// A run of consecutive lanes of one wave that work on one tile of one board:
+// lanes lane0 .. lane0 + nlanes - 1 hold logical dwords p0 .. p0 + nlanes - 1
+// of rows r0 - T .. r0 + h + T - 1; the first and last lane are halo, the
+// others write rows r0 .. r0 + h - 1.  Logical dword p covers the logical
+// columns 32 p .. 32 p + 31, and logical column x is cell x mod C (the torus
+// unrolled), so p may be -1 or reach past the row end.
+struct Segment {
+  int32_t board;
+  int32_t p0;
+  int32_t r0;
+  uint16_t h;
+  uint8_t lane0;
+  uint8_t nlanes;
+};
+
+// One wave's work in a launch: segments [seg_begin, seg_begin + nseg).
+struct WaveItem {
+  int32_t seg_begin;
+  int16_t nseg;
+  uint16_t h;      // max h over its segments
+  int32_t maxK;    // the wave takes part in levels 0 .. maxK - 1
+  int32_t flags;   // kItemAligned: every lane's board has C % 32 == 0
+};
+constexpr int32_t kItemAligned = 1;
+
+// Geometry of a single large board split into strips x bands, one wave per
+// tile, computed from the block index (no tables).
+struct GridGeom {
+  int32_t nstrips;   // strips across a row
+  int32_t nbands;    // bands down the board
+  int32_t strip_q, strip_r;  // balanced split of D dwords: first strip_r strips get q+1
+  int32_t band_q, band_r;    // balanced split of R rows
+};
+
+}  // namespace gol

@@ -1,0 +1,510 @@
+// HIP kernels for gfx950 (CDNA4): Conway's Life, B3/S23, on a torus.
+//
+// The method (the paper, Section 1): every cell has eight neighbours, all
+// cells change at once each time step, a live cell survives with two or three
+// live neighbours, a dead cell is born with exactly three.  The grid is a
+// torus (Section 2.2): rows and columns wrap.  Boards are bit-packed, one bit
+// per cell (see gol_internal.h for the layout).
+//
+// Tile pass.  One wave (64 lanes) owns a tile: a strip of consecutive 32-bit
+// column words ("dwords") and a band of rows.  Lane l holds logical dword
+// p0 + l of the rows it sweeps, top to bottom; the first and last lane of the
+// strip are halo.  The wave advances the tile by T generations in one sweep:
+// a T-stage pipeline held in registers, stage s turning generation s rows into
+// generation s + 1 rows one row behind stage s - 1.  Each stage keeps a
+// window of three rows.  Horizontal neighbour bits cross lanes with DPP
+// (wave_shr / wave_shl) and v_alignbit; the neighbour count and the rule are
+// a bit-sliced adder network of v_bitop3 ops (gfx950's 3-input logic op).
+//
+// Torus seam.  A lane's dword is a window of 32 logical columns, logical
+// column x being cell x mod C.  The window is gathered once per row at load
+// time (funnel shift across the seam for C not a multiple of 32), so the
+// generation pipeline itself never sees the seam and every board shape,
+// including tori narrower than 3 cells, takes the same path.  Rows wrap the
+// same way: the sweep reads rows r0 - T .. r0 + h + T - 1 modulo R.
+//
+// Halo.  A stage's lanes at the ends of a strip get wrong neighbour bits from
+// outside the strip; wrong bits move inward one column per generation, so
+// after T <= 32 generations the halo dwords absorb them and every inner lane
+// is exact.  Likewise the T extra rows above and below the band.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gol_internal.h"
+
+namespace gol {
+
+// ---------------------------------------------------------------------------
+// Bit-sliced logic.  v_bitop3_b32 computes any function of three inputs from
+// an 8-entry truth table; the table of f is f(0xF0, 0xCC, 0xAA).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kXor3 = (0xF0u ^ 0xCCu ^ 0xAAu) & 0xFFu;                               // 0x96
+constexpr uint32_t kMaj3 = ((0xF0u & 0xCCu) | (0xF0u & 0xAAu) | (0xCCu & 0xAAu)) & 0xFFu;   // 0xE8
+// e1(v, c0, u) = !v & (c0 ^ u)
+constexpr uint32_t kE1 = (~0xF0u & (0xCCu ^ 0xAAu)) & 0xFFu;                               // 0x06
+// e2(v, c0, u) = v ? (!c0 & !u) : (c0 & u)
+constexpr uint32_t kE2 = ((0xF0u & ~0xCCu & ~0xAAu) | (~0xF0u & 0xCCu & 0xAAu)) & 0xFFu;     // 0x18
+// sel(s, a, b) = s ? a : b
+constexpr uint32_t kSel = ((0xF0u & 0xCCu) | (~0xF0u & 0xAAu)) & 0xFFu;                    // 0xCA
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, kXor3);
+}
+__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, kMaj3);
+}
+
+// Next generation of a 32-cell dword from the horizontal 3-sums of the row
+// above (a), the row itself (c) and the row below (b), each sum as a 2-bit
+// number lo + 2 hi, and the row's own cells x.
+//   nine-cell sum  S = (lo_a+lo_c+lo_b) + 2 (hi_a+hi_c+hi_b)
+//                    = s0 + 2 (c0 + u + 2 v)
+//   live next  <=>  S == 3  or  (x and S == 4)
+//   S == 3  <=>  s0 and !v and (c0 ^ u)
+//   S == 4  <=>  !s0 and (v ? !c0 & !u : c0 & u)
+// (S counts the cell itself: 3 = birth or survival with two neighbours,
+// 4 with a live cell = survival with three neighbours.)
+__device__ __forceinline__ uint32_t life_rule(uint32_t lo_a, uint32_t lo_c, uint32_t lo_b,
+                                              uint32_t hi_a, uint32_t hi_c, uint32_t hi_b,
+                                              uint32_t x) {
+  const uint32_t s0 = xor3(lo_a, lo_c, lo_b);
+  const uint32_t c0 = maj3(lo_a, lo_c, lo_b);
+  const uint32_t u = xor3(hi_a, hi_c, hi_b);
+  const uint32_t v = maj3(hi_a, hi_c, hi_b);
+  const uint32_t e1 = __builtin_amdgcn_bitop3_b32(v, c0, u, kE1);
+  const uint32_t e2 = __builtin_amdgcn_bitop3_b32(v, c0, u, kE2);
+  const uint32_t f = x & e2;
+  return __builtin_amdgcn_bitop3_b32(s0, e1, f, kSel);
+}
+
+// Lane l receives src of lane l - 1 (lane 0 receives 0).
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+}
+// Lane l receives src of lane l + 1 (lane 63 receives 0).
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
+}
+
+// ---------------------------------------------------------------------------
+// Per-lane state of one tile sweep.
+// ---------------------------------------------------------------------------
+struct Lane {
+  const uint32_t* src;  // source board of this pass
+  uint32_t* dst;        // destination board of this pass
+  int32_t R, C, D;
+  // gather of the lane's 32 logical columns: first n1 bits start at cell q
+  // (dword ia, shift sh, continuing into dword ib), the rest come from the
+  // row start (dword 0); boards narrower than 32 cells take a bit loop.
+  int32_t ia, ib;
+  uint32_t sh, n1, q;
+  bool needB, needC, tiny;
+  bool live;            // lane has a board in this launch
+  // rows
+  int32_t in_r;
+  const uint32_t* in_row;
+  int32_t out_r;
+  uint32_t* out_row;
+  // store
+  bool store;
+  int32_t sidx;
+  uint32_t smask;
+  int32_t hl;           // rows this lane writes
+  int32_t Tl;           // generations this lane advances (masked pipelines)
+};
+
+__device__ __forceinline__ void lane_setup(Lane& L, const uint32_t* src, uint32_t* dst, int32_t R,
+                                           int32_t C, int32_t D, int32_t p, int32_t lane_in_seg,
+                                           int32_t nlanes, int32_t r0, int32_t h, int32_t T,
+                                           int32_t Tl, bool live) {
+  L.src = src;
+  L.dst = dst;
+  L.R = R;
+  L.C = C;
+  L.D = D;
+  L.live = live;
+  L.Tl = Tl;
+  int64_t q64 = ((int64_t)p * 32) % (int64_t)C;
+  if (q64 < 0) q64 += C;
+  const uint32_t q = (uint32_t)q64;
+  L.q = q;
+  L.tiny = C < 32;
+  const int32_t nd = (C + 31) >> 5;
+  if (!L.tiny) {
+    L.ia = (int32_t)(q >> 5);
+    L.sh = q & 31u;
+    L.n1 = (uint32_t)min((int64_t)32, (int64_t)C - (int64_t)q);
+    L.needB = L.sh != 0u && L.ia + 1 < nd;
+    L.ib = L.needB ? L.ia + 1 : L.ia;
+    L.needC = L.n1 < 32u;
+  } else {
+    L.ia = 0;
+    L.ib = 0;
+    L.sh = 0;
+    L.n1 = 32;
+    L.needB = false;
+    L.needC = false;
+  }
+  int64_t rin = ((int64_t)r0 - T) % (int64_t)R;
+  if (rin < 0) rin += R;
+  L.in_r = (int32_t)rin;
+  L.in_row = src + rin * (int64_t)D;
+  L.out_r = r0;
+  L.out_row = dst + (int64_t)r0 * D;
+  L.store = live && lane_in_seg >= 1 && lane_in_seg <= nlanes - 2 && p >= 0 && p < D;
+  L.sidx = p;
+  const int64_t c0 = (int64_t)p * 32;
+  L.smask = (c0 + 32 <= C) ? 0xFFFFFFFFu : (c0 >= C ? 0u : ((1u << (uint32_t)(C - c0)) - 1u));
+  L.hl = h;
+}
+
+struct Raw {
+  uint32_t a, b, c;
+};
+
+template <bool ALIGNED>
+__device__ __forceinline__ Raw load_raw(const Lane& L) {
+  Raw r{0u, 0u, 0u};
+  if (L.live) {
+    r.a = __builtin_nontemporal_load(L.in_row + L.ia);
+    if (!ALIGNED) {
+      if (L.needB) r.b = L.in_row[L.ib];
+      if (L.needC) r.c = L.in_row[0];
+    }
+  }
+  return r;
+}
+
+template <bool ALIGNED>
+__device__ __forceinline__ uint32_t window(const Raw& r, const Lane& L) {
+  if (ALIGNED) return r.a;
+  if (!L.tiny) {
+    uint32_t w = __builtin_amdgcn_alignbit(r.b, r.a, L.sh);
+    if (L.needC) w = (w & ((1u << L.n1) - 1u)) | (r.c << L.n1);
+    return w;
+  }
+  uint32_t w = 0u, pos = L.q;
+  for (int i = 0; i < 32; ++i) {
+    w |= ((r.a >> pos) & 1u) << i;
+    pos = (pos + 1u == (uint32_t)L.C) ? 0u : pos + 1u;
+  }
+  return w;
+}
+
+__device__ __forceinline__ void advance_in(Lane& L) {
+  L.in_r += 1;
+  L.in_row += L.D;
+  if (L.in_r == L.R) {
+    L.in_r = 0;
+    L.in_row = L.src;
+  }
+}
+
+__device__ __forceinline__ void advance_out(Lane& L) {
+  L.out_r += 1;
+  L.out_row += L.D;
+  if (L.out_r == L.R) {
+    L.out_r = 0;
+    L.out_row = L.dst;
+  }
+}
+
+template <int TM>
+struct Pipe {
+  uint32_t lo[TM][3];
+  uint32_t hi[TM][3];
+  uint32_t xs[TM][3];
+};
+
+// Stage S of the pipeline at a step of phase PH (step index mod 3).  Stage S
+// receives generation-S row m = step - S into slot m mod 3 and, once it holds
+// rows m - 2, m - 1, m, emits generation S + 1 of row m - 1 to stage S + 1.
+// In the prologue (PRO) the step index K is known at compile time and stages
+// that have not yet received (K < 2S) or cannot yet emit (K < 2S + 2) stop.
+template <int TM, bool MASKED, int PH, int S, bool PRO, int K>
+__device__ __forceinline__ void stages(uint32_t& x, Pipe<TM>& P, const Lane& L) {
+  if constexpr (S < TM) {
+    if constexpr (!(PRO && K < 2 * S)) {
+      constexpr int slot = ((PH - S) % 3 + 3) % 3;
+      constexpr int sa = (slot + 1) % 3;  // row m - 2
+      constexpr int sc = (slot + 2) % 3;  // row m - 1
+      const uint32_t xp = from_prev_lane(x);
+      const uint32_t xn = from_next_lane(x);
+      const uint32_t xl = __builtin_amdgcn_alignbit(x, xp, 31);  // west neighbours
+      const uint32_t xr = __builtin_amdgcn_alignbit(xn, x, 1);   // east neighbours
+      P.lo[S][slot] = xor3(xl, x, xr);
+      P.hi[S][slot] = maj3(xl, x, xr);
+      P.xs[S][slot] = x;
+      if constexpr (!(PRO && K < 2 * S + 2)) {
+        uint32_t y = life_rule(P.lo[S][sa], P.lo[S][sc], P.lo[S][slot], P.hi[S][sa], P.hi[S][sc],
+                               P.hi[S][slot], P.xs[S][sc]);
+        if (MASKED) y = (S < L.Tl) ? y : P.xs[S][sc];
+        x = y;
+        stages<TM, MASKED, PH, S + 1, PRO, K>(x, P, L);
+      }
+    }
+  }
+}
+
+template <int TM, bool MASKED, bool ALIGNED, int PH, bool PRO, int K>
+__device__ __forceinline__ void step(int i, int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[3]) {
+  uint32_t x = window<ALIGNED>(PF[PH], L);
+  if (i + 3 < nsteps) {
+    PF[PH] = load_raw<ALIGNED>(L);
+    advance_in(L);
+  }
+  stages<TM, MASKED, PH, 0, PRO, K>(x, P, L);
+  if constexpr (!PRO) {
+    // stage TM - 1 emitted generation TM of output row i - 2 TM of the band
+    if (L.store && i - 2 * TM < L.hl) __builtin_nontemporal_store(x & L.smask, L.out_row + L.sidx);
+    advance_out(L);
+  }
+}
+
+template <int TM, bool MASKED, bool ALIGNED, int K>
+__device__ __forceinline__ void prologue(int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[3]) {
+  if constexpr (K < 2 * TM) {
+    step<TM, MASKED, ALIGNED, K % 3, true, K>(K, nsteps, L, P, PF);
+    prologue<TM, MASKED, ALIGNED, K + 1>(nsteps, L, P, PF);
+  }
+}
+
+// Sweep one tile: H output rows (the wave's largest band), TM generations.
+template <int TM, bool MASKED, bool ALIGNED>
+__device__ void run_tile(Lane& L, int H) {
+  static_assert(TM >= 1 && TM <= kMaxT, "generations per pass");
+  Pipe<TM> P;
+  Raw PF[3];
+  const int nsteps = H + 2 * TM;  // >= 3
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    PF[k] = load_raw<ALIGNED>(L);
+    advance_in(L);
+  }
+  prologue<TM, MASKED, ALIGNED, 0>(nsteps, L, P, PF);
+  constexpr int P0 = (2 * TM) % 3, P1 = (2 * TM + 1) % 3, P2 = (2 * TM + 2) % 3;
+  int i = 2 * TM;
+  for (; i + 2 < nsteps; i += 3) {
+    step<TM, MASKED, ALIGNED, P0, false, 0>(i, nsteps, L, P, PF);
+    step<TM, MASKED, ALIGNED, P1, false, 0>(i + 1, nsteps, L, P, PF);
+    step<TM, MASKED, ALIGNED, P2, false, 0>(i + 2, nsteps, L, P, PF);
+  }
+  if (i < nsteps) step<TM, MASKED, ALIGNED, P0, false, 0>(i, nsteps, L, P, PF);
+  if (i + 1 < nsteps) step<TM, MASKED, ALIGNED, P1, false, 0>(i + 1, nsteps, L, P, PF);
+}
+
+// Workgroups are dealt to the 8 XCDs of the chip in turn; give each XCD a
+// contiguous range of items so tiles that share halo rows share an L2.
+__device__ __forceinline__ int xcd_item(int nitems) {
+  const int per = (nitems + 7) >> 3;
+  const int b = (int)blockIdx.x;
+  return (b & 7) * per + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// Single board: tile (strip s, band b) from the block index, no tables.
+// ---------------------------------------------------------------------------
+struct PassArgs {
+  const uint32_t* src;
+  uint32_t* dst;
+  int32_t R, C, D;
+};
+
+template <int TM>
+__global__ __launch_bounds__(64) void k_board_pass(PassArgs a, GridGeom g) {
+  const int nitems = g.nstrips * g.nbands;
+  const int item = xcd_item(nitems);
+  if (item >= nitems) return;  // whole wave
+  const int s = item % g.nstrips, b = item / g.nstrips;
+  const int us = g.strip_q + (s < g.strip_r ? 1 : 0);
+  const int ds = s * g.strip_q + min(s, g.strip_r);
+  const int hb = g.band_q + (b < g.band_r ? 1 : 0);
+  const int rb = b * g.band_q + min(b, g.band_r);
+  const int lane = (int)threadIdx.x;
+  const int nl = us + 2;
+  Lane L;
+  lane_setup(L, a.src, a.dst, a.R, a.C, a.D, ds - 1 + lane, lane, nl, rb, hb, TM, TM, lane < nl);
+  if ((a.C & 31) == 0)
+    run_tile<TM, false, true>(L, hb);
+  else
+    run_tile<TM, false, false>(L, hb);
+}
+
+// ---------------------------------------------------------------------------
+// Many boards: waves from a table, each made of one or more segments.
+// ---------------------------------------------------------------------------
+template <int TM, bool MASKED>
+__global__ __launch_bounds__(64) void k_batch_pass(const BoardDesc* __restrict__ boards,
+                                                   const Segment* __restrict__ segs,
+                                                   const WaveItem* __restrict__ items, int nitems,
+                                                   int level) {
+  const int it = xcd_item(nitems);
+  if (it >= nitems) return;  // whole wave
+  const WaveItem w = items[it];
+  const int lane = (int)threadIdx.x;
+  int mine = -1;
+  for (int k = 0; k < w.nseg; ++k) {
+    const Segment sg = segs[w.seg_begin + k];
+    if (lane >= sg.lane0 && lane < sg.lane0 + sg.nlanes) mine = w.seg_begin + k;
+  }
+  Lane L;
+  if (mine >= 0) {
+    const Segment sg = segs[mine];
+    const BoardDesc bd = boards[sg.board];
+    const bool active = level < bd.K;
+    const int j = active ? level : bd.K - 1;
+    const uint32_t* src = (j == 0) ? bd.src0 : bd.w[(j - 1 + bd.par) & 1];
+    uint32_t* dst = bd.w[(j + bd.par) & 1];
+    const int Tl = (j == 0) ? bd.Tfirst : TM;
+    lane_setup(L, src, dst, bd.R, bd.C, bd.D, sg.p0 + (lane - sg.lane0), lane - sg.lane0,
+               sg.nlanes, sg.r0, sg.h, TM, Tl, active);
+  } else {
+    const Segment sg = segs[w.seg_begin];
+    const BoardDesc bd = boards[sg.board];
+    lane_setup(L, bd.src0, bd.w[0], bd.R, bd.C, bd.D, 0, 0, 1, 0, 1, TM, TM, false);
+  }
+  if (w.flags & kItemAligned)
+    run_tile<TM, MASKED, true>(L, w.h);
+  else
+    run_tile<TM, MASKED, false>(L, w.h);
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion (byte boards of the host API) and normalising copies.
+// ---------------------------------------------------------------------------
+
+// uint8 cells (nonzero = alive) -> packed words.  One wave per output word:
+// lane l tests cell 64 w + l, the wave's ballot is the word.
+__global__ __launch_bounds__(256) void k_pack(const uint8_t* __restrict__ in, int64_t R, int64_t C,
+                                              int64_t W, uint64_t* __restrict__ out) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t wi = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); wi < R * W;
+       wi += nwaves) {
+    const int64_t r = wi / W, c = (wi - r * W) * 64 + lane;
+    const bool alive = c < C && in[r * C + c] != 0;
+    const uint64_t m = __ballot(alive);
+    if (lane == 0) out[wi] = m;
+  }
+}
+
+// packed words -> uint8 cells 0/1, one thread per cell.
+__global__ __launch_bounds__(256) void k_unpack(const uint64_t* __restrict__ in, int64_t R,
+                                                int64_t C, int64_t W, uint8_t* __restrict__ out) {
+  const int64_t n = R * C;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / C, c = i - r * C;
+    out[i] = (uint8_t)((in[r * W + (c >> 6)] >> (c & 63)) & 1u);
+  }
+}
+
+// Copy words with the padding bits (columns >= C) cleared.
+__global__ __launch_bounds__(256) void k_copy_clear_padding(const uint64_t* __restrict__ in,
+                                                            int64_t R, int64_t C, int64_t W,
+                                                            uint64_t* __restrict__ out) {
+  const int64_t n = R * W;
+  const int64_t last = C - (W - 1) * 64;  // valid bits of the last word, 1..64
+  const uint64_t lastmask = last >= 64 ? ~0ull : ((1ull << last) - 1ull);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = i % W;
+    out[i] = in[i] & (w == W - 1 ? lastmask : ~0ull);
+  }
+}
+
+// Fill 32-bit words (device counters, flags); used instead of hipMemsetAsync
+// so the launch sequences can be captured into graphs.
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n,
+                                                  uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (called by the C ABI in gol_capi.cpp).
+// ---------------------------------------------------------------------------
+template <int TM>
+static hipError_t launch_board_pass_t(const PassArgs& a, const GridGeom& g, hipStream_t st) {
+  const int nitems = g.nstrips * g.nbands;
+  const int grid = ((nitems + 7) / 8) * 8;
+  hipLaunchKernelGGL(k_board_pass<TM>, dim3(grid), dim3(64), 0, st, a, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
+                             int32_t D, const GridGeom& g, hipStream_t st) {
+  PassArgs a{src, dst, R, C, D};
+  switch (T) {
+    case 1: return launch_board_pass_t<1>(a, g, st);
+    case 2: return launch_board_pass_t<2>(a, g, st);
+    case 4: return launch_board_pass_t<4>(a, g, st);
+    case 8: return launch_board_pass_t<8>(a, g, st);
+    case 16: return launch_board_pass_t<16>(a, g, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int TM, bool MASKED>
+static hipError_t launch_batch_pass_t(const BoardDesc* boards, const Segment* segs,
+                                      const WaveItem* items, int nitems, int level,
+                                      hipStream_t st) {
+  const int grid = ((nitems + 7) / 8) * 8;
+  hipLaunchKernelGGL((k_batch_pass<TM, MASKED>), dim3(grid), dim3(64), 0, st, boards, segs, items,
+                     nitems, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_pass(int T, bool masked, const BoardDesc* boards, const Segment* segs,
+                             const WaveItem* items, int nitems, int level, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  switch (T) {
+    case 1: return masked ? launch_batch_pass_t<1, true>(boards, segs, items, nitems, level, st)
+                          : launch_batch_pass_t<1, false>(boards, segs, items, nitems, level, st);
+    case 2: return masked ? launch_batch_pass_t<2, true>(boards, segs, items, nitems, level, st)
+                          : launch_batch_pass_t<2, false>(boards, segs, items, nitems, level, st);
+    case 4: return masked ? launch_batch_pass_t<4, true>(boards, segs, items, nitems, level, st)
+                          : launch_batch_pass_t<4, false>(boards, segs, items, nitems, level, st);
+    case 8: return masked ? launch_batch_pass_t<8, true>(boards, segs, items, nitems, level, st)
+                          : launch_batch_pass_t<8, false>(boards, segs, items, nitems, level, st);
+    case 16: return masked ? launch_batch_pass_t<16, true>(boards, segs, items, nitems, level, st)
+                           : launch_batch_pass_t<16, false>(boards, segs, items, nitems, level, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+static int grid_for(int64_t n, int per_block) {
+  int64_t g = (n + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (int)g;
+}
+
+hipError_t launch_pack(const uint8_t* in, int64_t R, int64_t C, uint64_t* out, hipStream_t st) {
+  const int64_t W = (C + 63) / 64;
+  hipLaunchKernelGGL(k_pack, dim3(grid_for(R * W, 4)), dim3(256), 0, st, in, R, C, W, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const uint64_t* in, int64_t R, int64_t C, uint8_t* out, hipStream_t st) {
+  const int64_t W = (C + 63) / 64;
+  hipLaunchKernelGGL(k_unpack, dim3(grid_for(R * C, 256)), dim3(256), 0, st, in, R, C, W, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_clear_padding(const uint64_t* in, int64_t R, int64_t C, uint64_t* out,
+                                     hipStream_t st) {
+  const int64_t W = (C + 63) / 64;
+  hipLaunchKernelGGL(k_copy_clear_padding, dim3(grid_for(R * W, 256)), dim3(256), 0, st, in, R, C,
+                     W, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace gol

@@ -1,0 +1,182 @@
+// Host-side schedule of tile passes; see gol_plan.h.
+#include "gol_plan.h"
+
+#include <algorithm>
+#include <map>
+#include <numeric>
+
+namespace gol {
+
+bool valid_T(int T) { return T == 1 || T == 2 || T == 4 || T == 8 || T == 16; }
+
+static int64_t dwords_per_row(int64_t cols) { return 2 * ((cols + 63) / 64); }
+
+GridGeom board_geometry(int64_t rows, int64_t cols, int band_rows) {
+  const int64_t D = dwords_per_row(cols);
+  const int64_t ns = (D + kStripDwords - 1) / kStripDwords;
+  const int64_t nb = (rows + band_rows - 1) / band_rows;
+  const Split s = split(D, ns), b = split(rows, nb);
+  GridGeom g;
+  g.nstrips = (int32_t)ns;
+  g.nbands = (int32_t)nb;
+  g.strip_q = (int32_t)s.q;
+  g.strip_r = (int32_t)s.r;
+  g.band_q = (int32_t)b.q;
+  g.band_r = (int32_t)b.r;
+  return g;
+}
+
+std::vector<int> single_board_passes(int64_t generations, int T) {
+  std::vector<int> p;
+  const int64_t r = generations % T;
+  for (int k = 0; (1 << k) < T; ++k)
+    if (r & (1 << k)) p.push_back(1 << k);
+  for (int64_t i = 0; i < generations / T; ++i) p.push_back(T);
+  return p;
+}
+
+int default_band_rows(int64_t rows, int64_t cols, int T) {
+  const int64_t D = dwords_per_row(cols);
+  const int64_t ns = (D + kStripDwords - 1) / kStripDwords;
+  // about 2048 tiles (8 waves per compute unit) when the board allows it
+  int64_t h = rows * ns / 2048;
+  const int64_t lo = std::max<int64_t>(16, 4 * T);
+  h = std::max<int64_t>(h, lo);
+  h = std::min<int64_t>(h, 512);
+  h = std::min<int64_t>(h, rows);
+  return (int)std::max<int64_t>(h, 1);
+}
+
+namespace {
+struct ItemBuild {
+  std::vector<Segment> segs;
+  int lanes = 0;
+  int h = 0;
+  int maxK = 0;
+  bool aligned = true;
+};
+}  // namespace
+
+bool build_plan(const std::vector<BoardReq>& boards, int T, int band_rows, HostPlan& plan,
+                std::string& err) {
+  if (!valid_T(T)) {
+    err = "generations per pass must be 1, 2, 4, 8 or 16";
+    return false;
+  }
+  if (band_rows < 1 || band_rows > 65535) {
+    err = "band height out of range";
+    return false;
+  }
+  plan = HostPlan();
+  plan.T = T;
+  plan.band_rows = band_rows;
+  const size_t n = boards.size();
+  plan.K.assign(n, 0);
+  plan.Tfirst.assign(n, 0);
+  for (size_t b = 0; b < n; ++b) {
+    const BoardReq& q = boards[b];
+    if (q.rows < 1 || q.cols < 1 || q.rows > (1 << 30) || q.cols > (1 << 30) ||
+        q.generations < 0) {
+      err = "board " + std::to_string(b) + ": size or generations out of range";
+      return false;
+    }
+    const int64_t K = (q.generations + T - 1) / T;
+    if (K > (int64_t)1 << 30) {
+      err = "board " + std::to_string(b) + ": too many generations";
+      return false;
+    }
+    plan.K[b] = (int32_t)K;
+    plan.Tfirst[b] = K > 0 ? (int32_t)(q.generations - (K - 1) * T) : 0;
+    if (K > 0 && plan.Tfirst[b] < T) plan.level0_masked = true;
+    plan.cell_updates += (double)q.rows * (double)q.cols * (double)q.generations;
+  }
+  std::vector<int32_t> order;
+  for (size_t b = 0; b < n; ++b)
+    if (plan.K[b] > 0) order.push_back((int32_t)b);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t c) { return plan.K[a] > plan.K[c]; });
+
+  // First-fit packing of segments into 64-lane waves.  A segment joins an
+  // open wave if it fits, its band is at most an eighth shorter than the
+  // wave's tallest (the wave's row count is its tallest band), and its board
+  // needs at most max(2, maxK / 8) fewer passes than the wave's longest board
+  // (lanes of boards that finish early idle in later levels).
+  std::vector<ItemBuild> built;
+  std::vector<size_t> open;  // indices of waves that may still take segments
+  for (int32_t b : order) {
+    const BoardReq& q = boards[b];
+    const int64_t D = dwords_per_row(q.cols);
+    const int64_t ns = (D + kStripDwords - 1) / kStripDwords;
+    const Split S = split(D, ns);
+    const int64_t nb = (q.rows + band_rows - 1) / band_rows;
+    const Split B = split(q.rows, nb);
+    const int Kb = plan.K[b];
+    const bool aligned = (q.cols % 32) == 0;
+    // waves that can no longer take boards of this K close for good
+    open.erase(std::remove_if(open.begin(), open.end(),
+                              [&](size_t i) {
+                                return built[i].maxK - Kb > std::max(2, built[i].maxK / 8);
+                              }),
+               open.end());
+    for (int64_t bi = 0; bi < nb; ++bi) {
+      const int h = (int)B.size(bi);
+      for (int64_t si = 0; si < ns; ++si) {
+        Segment sg;
+        sg.board = b;
+        sg.p0 = (int32_t)(S.start(si) - 1);
+        sg.r0 = (int32_t)B.start(bi);
+        sg.h = (uint16_t)h;
+        sg.nlanes = (uint8_t)(S.size(si) + 2);
+        size_t pick = SIZE_MAX;
+        const size_t first = open.size() > 64 ? open.size() - 64 : 0;
+        for (size_t k = first; k < open.size(); ++k) {
+          const ItemBuild& it = built[open[k]];
+          if (it.lanes + sg.nlanes <= kWave && h <= it.h && h >= it.h - it.h / 8) {
+            pick = k;
+            break;
+          }
+        }
+        if (pick == SIZE_MAX) {
+          ItemBuild it;
+          it.h = h;
+          it.maxK = Kb;
+          built.push_back(std::move(it));
+          open.push_back(built.size() - 1);
+          pick = open.size() - 1;
+        }
+        ItemBuild& it = built[open[pick]];
+        sg.lane0 = (uint8_t)it.lanes;
+        it.segs.push_back(sg);
+        it.lanes += sg.nlanes;
+        it.aligned = it.aligned && aligned;
+        if (it.lanes > kWave - 3) open.erase(open.begin() + pick);
+      }
+    }
+  }
+  std::stable_sort(built.begin(), built.end(),
+                   [](const ItemBuild& a, const ItemBuild& c) { return a.maxK > c.maxK; });
+  plan.segs.clear();
+  plan.items.clear();
+  plan.items.reserve(built.size());
+  for (const ItemBuild& it : built) {
+    WaveItem w;
+    w.seg_begin = (int32_t)plan.segs.size();
+    w.nseg = (int16_t)it.segs.size();
+    w.h = (uint16_t)it.h;
+    w.maxK = it.maxK;
+    w.flags = it.aligned ? kItemAligned : 0;
+    plan.items.push_back(w);
+    plan.segs.insert(plan.segs.end(), it.segs.begin(), it.segs.end());
+  }
+  const int Kmax = built.empty() ? 0 : built.front().maxK;
+  plan.level_items.assign(Kmax, 0);
+  size_t cnt = plan.items.size();
+  for (int L = 0; L < Kmax; ++L) {
+    while (cnt > 0 && plan.items[cnt - 1].maxK <= L) --cnt;
+    plan.level_items[L] = (int32_t)cnt;
+    for (size_t i = 0; i < cnt; ++i) plan.lane_steps += (double)kWave * (plan.items[i].h + 2 * T);
+  }
+  return true;
+}
+
+}  // namespace gol

@@ -1,0 +1,69 @@
+// Host-side schedule of tile passes for one or many boards (no HIP calls).
+//
+// A board of G generations runs K = ceil(G / T) passes: pass 0 advances
+// G - (K - 1) T generations, every later pass T.  Boards run their passes
+// level by level: level L holds pass L of every board with K > L, so one
+// launch per level advances all boards still running, and a board that
+// needs fewer generations simply drops out of later levels.
+//
+// Tiles: a board's row of D dwords is cut into strips of at most 62 useful
+// dwords (each strip + 2 halo lanes fits a 64-lane wave), its rows into bands
+// of at most `band_rows` rows.  A tile is one segment of consecutive lanes.
+// Tiles of 32 lanes or more get a wave of their own; smaller ones (narrow
+// boards) are packed several to a wave, grouped by band height and by K so
+// that packed lanes stay busy.  Waves are sorted by their largest K, so the
+// waves of level L are a prefix of one array.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "gol_internal.h"
+
+namespace gol {
+
+struct BoardReq {
+  int64_t rows, cols, generations;
+};
+
+struct HostPlan {
+  int T = 8;
+  int band_rows = 64;
+  std::vector<Segment> segs;
+  std::vector<WaveItem> items;
+  std::vector<int32_t> level_items;  // waves taking part in level L
+  std::vector<int32_t> K;            // passes per board
+  std::vector<int32_t> Tfirst;       // generations of pass 0 per board
+  bool level0_masked = false;        // some board's pass 0 is shorter than T
+  double cell_updates = 0;           // sum rows * cols * generations
+  double lane_steps = 0;             // sum over levels of waves * 64 * row steps
+};
+
+// Balanced split of n into k parts: part i has q + (i < r) items and starts
+// at i q + min(i, r).
+struct Split {
+  int64_t q, r;
+  int64_t size(int64_t i) const { return q + (i < r ? 1 : 0); }
+  int64_t start(int64_t i) const { return i * q + (i < r ? i : r); }
+};
+inline Split split(int64_t n, int64_t k) { return Split{n / k, n % k}; }
+
+// Grid of one large board for the single-board kernel.
+GridGeom board_geometry(int64_t rows, int64_t cols, int band_rows);
+
+// Pass lengths of a single board: powers of two for G mod T (small first),
+// then whole T passes.  Sum = G.
+std::vector<int> single_board_passes(int64_t generations, int T);
+
+// Builds the batch schedule.  Returns false with a message on invalid input.
+bool build_plan(const std::vector<BoardReq>& boards, int T, int band_rows, HostPlan& plan,
+                std::string& err);
+
+// Default band height for the single-board kernel: tall bands amortise the
+// 2T halo rows, but enough tiles are needed to fill 256 compute units.
+int default_band_rows(int64_t rows, int64_t cols, int T);
+
+bool valid_T(int T);
+
+}  // namespace gol

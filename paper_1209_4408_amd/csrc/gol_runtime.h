@@ -1,0 +1,52 @@
+// Runtime helpers shared by the C ABI translation units: error reporting,
+// stream-ordered device scratch, deferred release of pinned staging, and
+// the single-board / batch drivers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "gol.h"
+#include "gol_internal.h"
+#include "gol_plan.h"
+
+namespace gol {
+
+int set_error(int code, const char* fmt, ...);
+int hip_error(hipError_t e, const char* what);
+void clear_error();
+const char* last_error();
+
+int scratch_alloc(void** p, size_t bytes, hipStream_t st);
+void scratch_free(void* p, hipStream_t st);
+int defer_host_free(void* pinned, hipStream_t st);
+void reap_deferred(bool wait);
+
+int check_board(int64_t rows, int64_t cols, int64_t gens);
+bool ranges_partially_overlap(const void* a, const void* b, size_t bytes);
+int default_T();
+
+int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t* d_out,
+                hipStream_t st, int T, int band_rows);
+
+// A batch schedule bound to device buffers.
+struct DevicePlan {
+  HostPlan hp;
+  std::vector<gol_board> boards;
+  std::vector<BoardDesc> h_boards;
+  std::vector<int> copy_first;  // in-place boards with an odd pass count: copy in -> scratch
+  std::vector<int> zero_gen;    // generations == 0: normalising copy
+  BoardDesc* d_boards = nullptr;
+  Segment* d_segs = nullptr;
+  WaveItem* d_items = nullptr;
+  uint64_t* d_scratch = nullptr;
+  size_t scratch_words = 0;
+  std::vector<size_t> scratch_off;
+};
+
+int plan_boards(const gol_board* boards, int64_t n, int T, int band_rows, DevicePlan& P);
+void fill_board_descs(DevicePlan& P);
+hipError_t enqueue_plan(const DevicePlan& P, hipStream_t st);
+
+}  // namespace gol

@@ -1,0 +1,142 @@
+"""Host-side checks of the C ABI (no GPU): symbols, argument errors, the planner."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1209_4408_amd as gol
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"\b(gol_[a-z0-9_]+)\s*\(", src):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(gol.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_error_string():
+    assert "gfx950" in gol.version()
+    assert isinstance(gol.lib().gol_last_error(), bytes)
+
+
+@pytest.mark.parametrize("rows,cols,gens", [(0, 5, 1), (5, 0, 1), (3, 3, -1), (1 << 31, 4, 1)])
+def test_step_rejects_bad_sizes(rows, cols, gens):
+    buf = np.zeros(16, np.uint8)
+    rc = gol.lib().gol_step(buf.ctypes.data, rows, cols, gens, buf.ctypes.data)
+    assert rc == gol.GOL_EINVAL
+    assert gol.lib().gol_last_error()
+
+
+def test_step_rejects_null_and_partial_overlap():
+    buf = np.zeros(64, np.uint8)
+    assert gol.lib().gol_step(None, 4, 4, 1, buf.ctypes.data) == gol.GOL_EINVAL
+    assert gol.lib().gol_step(buf.ctypes.data, 4, 4, 1, buf.ctypes.data + 3) == gol.GOL_EINVAL
+
+
+def test_packed_rejects_bad_arguments():
+    L = gol.lib()
+    assert L.gol_step_packed(None, 4, 4, 1, 8, None) == gol.GOL_EINVAL
+    assert L.gol_step_packed_ex(8, 4, 4, 1, 16, None, 3) == gol.GOL_EINVAL  # bad t_block
+    assert L.gol_step_packed(8, 4, 70, 1, 16, None) == gol.GOL_EINVAL      # partial overlap
+    assert L.gol_step_packed(8, 4, 4, -2, 64, None) == gol.GOL_EINVAL
+
+
+def test_serve_create_rejects_bad_config():
+    L = gol.lib()
+    h = ctypes.c_void_p()
+    bad = [gol.ServeConfig(1 << 20, 0, 0, 0, 0), gol.ServeConfig(0, 8, 0, 0, 0),
+           gol.ServeConfig(1 << 20, 8, 0, 0, 3)]
+    for cfg in bad:
+        assert L.gol_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == gol.GOL_EINVAL
+    assert L.gol_serve_poll(None, 1, None, None) == gol.GOL_EINVAL
+
+
+def test_set_allocator_pairs():
+    L = gol.lib()
+    fn = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)(
+        lambda n, s, c: None)
+    assert L.gol_set_allocator(ctypes.cast(fn, ctypes.c_void_p), None, None) == gol.GOL_EINVAL
+    assert L.gol_set_allocator(None, None, None) == gol.GOL_OK
+
+
+# ---------------------------------------------------------------------------
+# Planner
+# ---------------------------------------------------------------------------
+def check_plan(rows, cols, gens, T, band):
+    segs, items, levels = gol.plan_tables(rows, cols, gens, T, band)
+    n = len(rows)
+    K = [(g + T - 1) // T for g in gens]
+    # every useful (row, dword) of every running board is written by exactly one lane
+    cover = {b: np.zeros((rows[b], 2 * ((cols[b] + 63) // 64)), np.int32) for b in range(n)
+             if K[b] > 0}
+    for it in items:
+        lanes = 0
+        ss = segs[it["seg_begin"]: it["seg_begin"] + it["nseg"]]
+        assert it["nseg"] >= 1
+        mk = 0
+        for s in ss:
+            assert s["lane0"] == lanes, "segments are packed left to right"
+            lanes += int(s["nlanes"])
+            assert s["nlanes"] >= 3 and s["h"] >= 1 and s["h"] <= it["h"]
+            b = int(s["board"])
+            mk = max(mk, K[b])
+            D = 2 * ((cols[b] + 63) // 64)
+            useful = np.arange(s["p0"] + 1, s["p0"] + s["nlanes"] - 1)
+            assert useful.min() >= 0 and useful.max() < D
+            cover[b][s["r0"]: s["r0"] + s["h"], useful] += 1
+            if it["flags"] & 1:
+                assert cols[b] % 32 == 0
+        assert lanes <= 64
+        assert it["maxK"] == mk
+    for b, c in cover.items():
+        assert (c == 1).all(), f"board {b} not covered exactly once"
+    # waves sorted by levels, level L launches the waves with maxK > L (a prefix)
+    mk = items["maxK"]
+    assert (np.diff(mk) <= 0).all()
+    assert len(levels) == (max(K) if K else 0)
+    for L, cnt in enumerate(levels):
+        assert cnt == int((mk > L).sum())
+    return segs, items, levels
+
+
+@pytest.mark.parametrize("T", [1, 4, 8, 16])
+def test_plan_covers_mixed_boards(T):
+    rng = np.random.default_rng(5)
+    rows = [int(x) for x in rng.integers(1, 300, 40)] + [1, 2, 3, 16384]
+    cols = [int(x) for x in rng.integers(1, 3000, 40)] + [1, 2, 33, 16384]
+    gens = [int(x) for x in rng.integers(0, 50, 40)] + [5, 0, 7, 3]
+    check_plan(rows, cols, gens, T, 64)
+
+
+def test_plan_batched_mix_shape():
+    import seeded_inputs
+    specs = seeded_inputs.batch_specs(1209, n=512)
+    rows = [s.rows for s in specs]
+    cols = [s.cols for s in specs]
+    gens = [s.generations for s in specs]
+    segs, items, levels = check_plan(rows, cols, gens, 8, 64)
+    lanes_used = sum(int(s["nlanes"]) for s in segs)
+    assert lanes_used / (64 * len(items)) > 0.7  # narrow boards share waves
+
+
+def test_plan_rejects_bad_input():
+    with pytest.raises(gol.GolError):
+        gol.plan_tables([4], [4], [-1])
+    with pytest.raises(gol.GolError):
+        gol.plan_tables([4], [4], [3], t_block=3)

@@ -1,0 +1,93 @@
+"""GPU: many boards in one schedule, and plans replayed from a HIP graph."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1209_4408_amd as gol
+import seeded_inputs
+from gpu_util import expect_words, first_diff, from_dev, rand_bytes, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def mixed_specs(seed, n):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        R = int(rng.integers(1, 200))
+        C = int(rng.choice([int(rng.integers(1, 70)), int(rng.integers(70, 2500))]))
+        G = int(rng.integers(0, 40))
+        out.append((R, C, G))
+    return out
+
+
+@pytest.mark.parametrize("T", [1, 4, 8, 16])
+def test_batch_matches_oracle(T):
+    specs = mixed_specs(T, 60)
+    boards, ins, outs, want = [], [], [], []
+    for i, (R, C, G) in enumerate(specs):
+        b = rand_bytes(4408, i, R, C, 0.4)
+        d_in = to_dev(oracle.pack(b))
+        d_out = gol.empty_packed(R, C)
+        boards.append(gol.BatchBoard(d_in, d_out, R, C, G))
+        want.append(expect_words(b, G))
+    say("batch T", T, "n", len(boards))
+    p = gol.Plan(boards, t_block=T)
+    p.run()
+    for i, bb in enumerate(boards):
+        got = from_dev(bb.d_out)
+        assert np.array_equal(got, want[i]), (i, specs[i], first_diff(got, want[i], specs[i][1]))
+    p.close()
+
+
+def test_batch_run_one_shot_and_inplace():
+    specs = mixed_specs(99, 30)
+    boards, want = [], []
+    for i, (R, C, G) in enumerate(specs):
+        b = rand_bytes(7, i, R, C, 0.5)
+        d = to_dev(oracle.pack(b))
+        boards.append(gol.BatchBoard(d, d, R, C, G))  # in place
+        want.append(expect_words(b, G))
+    gol.batch_run(boards)
+    for i, bb in enumerate(boards):
+        assert np.array_equal(from_dev(bb.d_out), want[i]), (i, specs[i])
+
+
+def test_plan_graph_replays():
+    """Replaying the captured plan from the same input gives the same result
+    every time, with the program's own work in between."""
+    import torch
+    specs = [(100, 300, 17), (64, 64, 8), (5, 2000, 3), (130, 77, 25)]
+    boards, want = [], []
+    for i, (R, C, G) in enumerate(specs):
+        b = rand_bytes(3, i, R, C, 0.4)
+        boards.append(gol.BatchBoard(to_dev(oracle.pack(b)), gol.empty_packed(R, C), R, C, G))
+        want.append(expect_words(b, G))
+    s = torch.cuda.Stream()
+    p = gol.Plan(boards)
+    for rep in range(4):
+        with torch.cuda.stream(s):
+            for bb in boards:
+                bb.d_out.zero_()
+            p.run(s)
+        s.synchronize()
+        junk = torch.randn(1000, device="cuda").sum().item()  # other eager work
+        assert np.isfinite(junk)
+        for i, bb in enumerate(boards):
+            assert np.array_equal(from_dev(bb.d_out), want[i]), (rep, i)
+    p.close()
+
+
+def test_mix_equals_alone():
+    """Each board gives the same result in a mix as when run alone."""
+    specs = seeded_inputs.batch_specs(1209, n=48, side_hi=600, gen_hi=60)
+    mix, alone = [], []
+    for s in specs:
+        w = seeded_inputs.board_packed(1209, s.board_id, s.rows, s.cols, s.p)
+        d_in = to_dev(w)
+        mix.append(gol.BatchBoard(d_in, gol.empty_packed(s.rows, s.cols), s.rows, s.cols,
+                                  s.generations))
+        alone.append(gol.step_packed(d_in, s.rows, s.cols, s.generations))
+    gol.batch_run(mix)
+    for s, m, a in zip(specs, mix, alone):
+        assert np.array_equal(from_dev(m.d_out), from_dev(a)), s
