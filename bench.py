@@ -137,15 +137,174 @@ def single_board(args, R, C, G, p, label):
     return res, extra
 
 
+def board_set_device(specs, seed):
+    """All boards of a mix in one device buffer (inputs) and one for outputs."""
+    import torch
+    import seeded_inputs
+    sizes = [s.rows * ((s.cols + 63) // 64) for s in specs]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    host = np.empty(int(offs[-1]), dtype=np.uint64)
+    for s, o, n in zip(specs, offs[:-1], sizes):
+        seeded_inputs.board_packed(seed, s.board_id, s.rows, s.cols, s.p,
+                                   out=host[o:o + n].reshape(s.rows, -1))
+    d_in = torch.from_numpy(host.view(np.int64)).cuda()
+    d_out = torch.empty_like(d_in)
+    ins = [d_in[o:o + n].view(s.rows, -1) for s, o, n in zip(specs, offs[:-1], sizes)]
+    outs = [d_out[o:o + n].view(s.rows, -1) for s, o, n in zip(specs, offs[:-1], sizes)]
+    return host, d_in, d_out, ins, outs
+
+
+def batched(args):
+    """4096 boards of uneven sizes and generation counts: one batched schedule
+    (graph replay) against the plain path, one gol_step_packed per board."""
+    import torch
+    import paper_1209_4408_amd as gol
+    import seeded_inputs
+    specs = seeded_inputs.batch_specs(SEED, n=args.boards)
+    work = float(sum(s.rows * s.cols * s.generations for s in specs))
+    log(f"generating {len(specs)} boards, {work:.3e} cell-updates")
+    _, d_in, d_out, ins, outs = board_set_device(specs, SEED)
+    T = args.t_block or 8
+    boards = [gol.BatchBoard(i, o, s.rows, s.cols, s.generations) for s, i, o in zip(specs, ins, outs)]
+    st = torch.cuda.Stream()
+    plan = gol.Plan(boards, t_block=T)
+    info = plan.info()
+    with torch.cuda.stream(st):
+        for _ in range(args.warmup):
+            plan.run(st)
+        st.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(st)
+        for _ in range(args.steps):
+            plan.run(st)
+        e1.record(st)
+        st.synchronize()
+        wall = time.perf_counter() - t0
+    dev = e0.elapsed_time(e1) / 1e3
+    value = work * args.steps / wall
+    # plain: one launch sequence per board, sequential on one stream
+    log("plain per-board loop")
+    with torch.cuda.stream(st):
+        for s, i, o in zip(specs, ins, outs):
+            gol.step_packed(i, s.rows, s.cols, s.generations, o, stream=st, t_block=T)
+        st.synchronize()
+        t0 = time.perf_counter()
+        for s, i, o in zip(specs, ins, outs):
+            gol.step_packed(i, s.rows, s.cols, s.generations, o, stream=st, t_block=T)
+        st.synchronize()
+        wall_plain = time.perf_counter() - t0
+    plain = work / wall_plain
+    plan.close()
+    # the batch kernel: algorithmic ops over the whole schedule / its device time
+    levels = info["levels"]
+    res = {"value": value, "wall_s": wall, "dev_s": dev,
+           "roofline": roofline_alu_total(work, dev / args.steps, levels, T)}
+    extra = {"plain": {"value": plain, "unit": "cell-updates/s",
+                       "what": "one gol_step_packed per board, sequential, same stream"},
+             "speedup_vs_plain": value / plain, "plan": info}
+    return res, extra
+
+
+def roofline_alu_total(work, dev_s, launches, T):
+    ops = OPS_PER_CELL_UPDATE * work
+    achieved = ops / dev_s / 1e12
+    peak = VALU_PEAK_OPS / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+            "frac": achieved / peak, "traffic": None, "kernel": f"k_batch_pass<{T}>",
+            "avg_launch_us": dev_s / max(1, launches) * 1e6, "launches": launches,
+            "ops_per_schedule": ops}
+
+
+def host_api(args):
+    """256 x 256 byte board, 100 generations through gol_step (host memory in
+    and out), plus the same board on the packed device path."""
+    import torch
+    import paper_1209_4408_amd as gol
+    import seeded_inputs
+    R = C = 256
+    G = 100
+    b = seeded_inputs.board_bytes(SEED, 0, R, C, 0.5)
+    out = np.empty_like(b)
+    for _ in range(max(3, args.warmup)):
+        gol.step(b, G, out=out)
+    lat = []
+    for _ in range(max(20, args.steps)):
+        t0 = time.perf_counter()
+        gol.step(b, G, out=out)
+        lat.append(time.perf_counter() - t0)
+    lat = np.array(lat)
+    import oracle
+    w = oracle.pack(b)
+    d_in = torch.from_numpy(w.view(np.int64)).cuda()
+    d_out = torch.empty_like(d_in)
+    wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, 20, 3, args.t_block or 8)
+    res = {"value": R * C * G / float(np.median(lat)), "wall_s": float(lat.sum()),
+           "dev_s": dev, "roofline": None}
+    extra = {"host_api_us": {"p50": float(np.median(lat) * 1e6),
+                             "p99": float(np.percentile(lat, 99, method="nearest") * 1e6)},
+             "device_us_per_call": dev / 20 * 1e6}
+    return res, extra, len(lat)
+
+
+def copy_calibration(args):
+    """A plain copy kernel of known size (generations = 0): what the FETCH_SIZE
+    and WRITE_SIZE counters read for 512 MiB in and 512 MiB out (larger than
+    the L2 and the Infinity Cache, so every byte comes from HBM)."""
+    import torch
+    import paper_1209_4408_amd as gol
+    R = C = 65536
+    d_in = torch.zeros((R, C // 64), dtype=torch.int64, device="cuda")
+    d_out = torch.empty_like(d_in)
+    for _ in range(args.steps):
+        gol.step_packed(d_in, R, C, 0, d_out)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": R * C // 8, "launches": args.steps}), flush=True)
+
+
+def sweep(args):
+    """Single-board tuning sweep: generations per pass x band count x prefetch.
+    Band counts put the wave total just under a multiple of the SIMD count."""
+    import torch
+    import paper_1209_4408_amd as gol
+    import seeded_inputs
+    R, C, G, p = (65536, 65536, 200, 0.5) if args.workload == "c3" else (16384, 16384, 1000, 0.3)
+    w = seeded_inputs.board_packed(SEED, 0, R, C, p)
+    d_in = torch.from_numpy(w.view(np.int64)).cuda()
+    del w
+    d_out = torch.empty_like(d_in)
+    nsimd = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    D = 2 * ((C + 63) // 64)
+    nstrips = (D + 61) // 62
+    for T in (4, 8, 16):
+        for pd in (3, 6):
+            os.environ["GOL_PREFETCH"] = str(pd)
+            for k in (1, 2, 3, 4, 6, 8, 12, 16):
+                bands = max(1, (k * nsimd) // nstrips)
+                h = -(-R // bands)
+                if h < 8:
+                    continue
+                os.environ["GOL_BAND_ROWS"] = str(h)
+                wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, 3, 1, T)
+                print(json.dumps({"T": T, "pd": pd, "k": k, "band_rows": h,
+                                  "waves": nstrips * (-(-R // h)),
+                                  "cell_updates_per_s": R * C * G * 3 / dev}), flush=True)
+    os.environ.pop("GOL_PREFETCH", None)
+    os.environ.pop("GOL_BAND_ROWS", None)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "copy"])
+    ap.add_argument("--boards", type=int, default=4096)
     ap.add_argument("--t-block", type=int, default=0)
     ap.add_argument("--compare-t1", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time T in {2,4,8,16} x band heights for the single-board workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding "
@@ -156,6 +315,8 @@ def main():
     assert torch.cuda.is_available(), "needs a HIP device"
     torch.cuda.set_device(0)
 
+    if args.sweep:
+        return sweep(args)
     if args.workload == "c2":
         R = C = 16384
         G, p = 1000, 0.3
@@ -167,8 +328,21 @@ def main():
         args.compare_t1 = True
         res, extra = single_board(args, R, C, G, p, "c3")
         workload = "65536x65536 torus, bit-packed, Bernoulli(0.5), 200 generations"
-    else:
-        raise SystemExit("workload not implemented yet")
+    elif args.workload == "c4":
+        res, extra = batched(args)
+        R = C = None
+        G, p = None, None
+        workload = (f"{args.boards} boards, rows/cols log-uniform [64, 2048], p U(0.1, 0.6), "
+                    "generations U{10..1000}, one batched schedule")
+    elif args.workload == "c1":
+        res, extra, n = host_api(args)
+        args.steps = n
+        R = C = 256
+        G, p = 100, 0.5
+        workload = "256x256 torus, uint8 cells, Bernoulli(0.5), 100 generations, host API"
+    elif args.workload == "copy":
+        copy_calibration(args)
+        return
     ms = res["wall_s"] / args.steps * 1e3
     line = {
         "metric": "cell-updates/sec",
@@ -190,7 +364,8 @@ def main():
     line.update(extra)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        line["cpu_baseline"] = cpu_baseline(min(R, 16384), min(C, 16384), p, SEED)
+        if args.workload in ("c2", "c3", "c1"):
+            line["cpu_baseline"] = cpu_baseline(min(R, 16384), min(C, 16384), p, SEED)
     print(json.dumps(line), flush=True)
 
 

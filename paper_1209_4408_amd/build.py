@@ -30,12 +30,13 @@ def _run(cmd: list[str]) -> None:
         raise RuntimeError("build step failed: " + " ".join(cmd))
 
 
-def build(save_temps: bool = False) -> str:
+def build(save_temps: bool = False, out: str = LIB, defines: tuple = ()) -> str:
     os.makedirs(OBJ, exist_ok=True)
     objs = []
     for s in DEVICE_SOURCES:
         o = os.path.join(OBJ, s + ".o")
-        cmd = [HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, s), "-o", o]
+        cmd = [HIPCC, *COMMON, *DEVICE, *[f"-D{d}" for d in defines], "-c",
+               os.path.join(CSRC, s), "-o", o]
         if save_temps:
             cmd += ["-save-temps=obj"]
         _run(cmd)
@@ -44,10 +45,10 @@ def build(save_temps: bool = False) -> str:
         o = os.path.join(OBJ, s + ".o")
         _run([HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, s), "-o", o])
         objs.append(o)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -2,6 +2,7 @@
 // plans.  Declared in include/gol.h.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
@@ -22,7 +23,7 @@ namespace gol {
 
 // Launchers defined in gol_kernels.hip.
 hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
-                             int32_t D, const GridGeom& g, hipStream_t st);
+                             int32_t D, const GridGeom& g, int pd, hipStream_t st);
 hipError_t launch_batch_pass(int T, bool masked, const BoardDesc* boards, const Segment* segs,
                              const WaveItem* items, int nitems, int level, hipStream_t st);
 hipError_t launch_pack(const uint8_t* in, int64_t R, int64_t C, uint64_t* out, hipStream_t st);
@@ -166,6 +167,24 @@ bool ranges_partially_overlap(const void* a, const void* b, size_t bytes) {
 
 int default_T() { return 8; }
 
+// SIMDs of the current device (4 per compute unit), cached per device.
+int simd_count() {
+  static std::mutex mu;
+  static std::vector<int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+  if (!cache[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    cache[dev] = 4 * cus;
+  }
+  return cache[dev];
+}
+
 // ---------------------------------------------------------------------------
 // Single board
 // ---------------------------------------------------------------------------
@@ -206,9 +225,17 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
     const uint32_t* src = (j == 0) ? src0 : w[(j - 1 + par) & 1];
     uint32_t* dst = w[(j + par) & 1];
     const int Tj = passes[j];
-    const int br = band_rows > 0 ? band_rows : default_band_rows(R, C, Tj);
+    int br = band_rows > 0 ? band_rows : default_band_rows(R, C, Tj, simd_count());
+    if (band_rows <= 0) {
+      // tuning override: GOL_BAND_ROWS=<rows>
+      const char* e = getenv("GOL_BAND_ROWS");
+      const int env_rows = e ? atoi(e) : 0;
+      if (env_rows > 0) br = env_rows;
+    }
     const GridGeom g = board_geometry(R, C, br);
-    e = launch_board_pass(Tj, src, dst, (int32_t)R, (int32_t)C, (int32_t)D, g, st);
+    const char* pe = getenv("GOL_PREFETCH");  // tuning override: 3 or 6
+    const int pd = pe ? atoi(pe) : default_prefetch(Tj);
+    e = launch_board_pass(Tj, src, dst, (int32_t)R, (int32_t)C, (int32_t)D, g, pd, st);
   }
   scratch_free(s1v, st);
   if (e != hipSuccess) return hip_error(e, "tile pass launch");

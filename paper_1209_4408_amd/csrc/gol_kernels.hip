@@ -32,6 +32,12 @@
 
 #include "gol_internal.h"
 
+// Which instruction kinds the scheduler may move across a row step's load
+// request (0: none, so the request stays PD steps ahead of its use).
+#ifndef GOL_PREFETCH_FENCE_MASK
+#define GOL_PREFETCH_FENCE_MASK 0
+#endif
+
 namespace gol {
 
 // ---------------------------------------------------------------------------
@@ -79,11 +85,11 @@ __device__ __forceinline__ uint32_t life_rule(uint32_t lo_a, uint32_t lo_c, uint
 
 // Lane l receives src of lane l - 1 (lane 0 receives 0).
 __device__ __forceinline__ uint32_t from_prev_lane(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138 /* wave_shr:1 */, 0xF, 0xF, true);
 }
 // Lane l receives src of lane l + 1 (lane 63 receives 0).
 __device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130 /* wave_shl:1 */, 0xF, 0xF, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -107,7 +113,7 @@ struct Lane {
   uint32_t* out_row;
   // store
   bool store;
-  int32_t sidx;
+  uint32_t soff;        // byte offset of the lane's dword in a row
   uint32_t smask;
   int32_t hl;           // rows this lane writes
   int32_t Tl;           // generations this lane advances (masked pipelines)
@@ -152,7 +158,7 @@ __device__ __forceinline__ void lane_setup(Lane& L, const uint32_t* src, uint32_
   L.out_r = r0;
   L.out_row = dst + (int64_t)r0 * D;
   L.store = live && lane_in_seg >= 1 && lane_in_seg <= nlanes - 2 && p >= 0 && p < D;
-  L.sidx = p;
+  L.soff = L.store ? (uint32_t)p * 4u : 0u;
   const int64_t c0 = (int64_t)p * 32;
   L.smask = (c0 + 32 <= C) ? 0xFFFFFFFFu : (c0 >= C ? 0u : ((1u << (uint32_t)(C - c0)) - 1u));
   L.hl = h;
@@ -162,15 +168,19 @@ struct Raw {
   uint32_t a, b, c;
 };
 
+// Every lane loads every step from an address inside the board (idle lanes
+// and lanes whose gather needs fewer words read valid words they ignore), so
+// the loads carry no branch and the compiler can wait for each one alone.
 template <bool ALIGNED>
 __device__ __forceinline__ Raw load_raw(const Lane& L) {
-  Raw r{0u, 0u, 0u};
-  if (L.live) {
-    r.a = __builtin_nontemporal_load(L.in_row + L.ia);
-    if (!ALIGNED) {
-      if (L.needB) r.b = L.in_row[L.ib];
-      if (L.needC) r.c = L.in_row[0];
-    }
+  Raw r;
+  r.a = L.in_row[L.ia];
+  if (!ALIGNED) {
+    r.b = L.in_row[L.ib];
+    r.c = L.in_row[0];
+  } else {
+    r.b = 0u;
+    r.c = 0u;
   }
   return r;
 }
@@ -179,6 +189,8 @@ template <bool ALIGNED>
 __device__ __forceinline__ uint32_t window(const Raw& r, const Lane& L) {
   if (ALIGNED) return r.a;
   if (!L.tiny) {
+    // ib == ia when the window ends inside dword ia; the bits rotated in
+    // above it are then replaced by the wrapped part below.
     uint32_t w = __builtin_amdgcn_alignbit(r.b, r.a, L.sh);
     if (L.needC) w = (w & ((1u << L.n1) - 1u)) | (r.c << L.n1);
     return w;
@@ -246,51 +258,99 @@ __device__ __forceinline__ void stages(uint32_t& x, Pipe<TM>& P, const Lane& L) 
   }
 }
 
-template <int TM, bool MASKED, bool ALIGNED, int PH, bool PRO, int K>
-__device__ __forceinline__ void step(int i, int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[3]) {
-  uint32_t x = window<ALIGNED>(PF[PH], L);
-  if (i + 3 < nsteps) {
-    PF[PH] = load_raw<ALIGNED>(L);
-    advance_in(L);
-  }
-  stages<TM, MASKED, PH, 0, PRO, K>(x, P, L);
+// One row step.  P3 = step index mod 3 (stage slots), PP = step index mod PD
+// (the prefetch ring: the row consumed now was loaded PD steps earlier, and
+// the row PD steps ahead is requested in its place).
+// Buffer descriptor word 3 for untyped 32-bit buffer access on gfx9-family
+// parts; offsets at or past num_records are dropped by the range check.
+constexpr int kBufferDword3 = 0x00020000;
+constexpr uint32_t kDroppedOffset = 0x80000000u;
+
+// A pointer that is the same in every lane, moved to scalar registers.
+// __builtin_amdgcn_readfirstlane takes and returns 32 bits, so the two halves
+// of the 64-bit address are read separately.
+__device__ __forceinline__ uint32_t* uniform_ptr(uint32_t* p) {
+  const uint64_t v = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (uint32_t*)(uintptr_t)(((uint64_t)hi << 32) | (uint64_t)lo);
+}
+
+template <int TM, bool MASKED, bool ALIGNED, int PD, bool BUFST, int P3, int PP, bool PRO, int K>
+__device__ __forceinline__ void step(int i, int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[PD]) {
+  uint32_t x = window<ALIGNED>(PF[PP], L);
+  // rows wrap, so the PD rows requested past the band's end are valid too
+  PF[PP] = load_raw<ALIGNED>(L);
+  advance_in(L);
+  // keep the request here, PD steps ahead of its use (the mask says which
+  // instruction kinds the scheduler may still move across this point)
+  __builtin_amdgcn_sched_barrier(GOL_PREFETCH_FENCE_MASK);
+  stages<TM, MASKED, P3, 0, PRO, K>(x, P, L);
   if constexpr (!PRO) {
     // stage TM - 1 emitted generation TM of output row i - 2 TM of the band
-    if (L.store && i - 2 * TM < L.hl) __builtin_nontemporal_store(x & L.smask, L.out_row + L.sidx);
+    if constexpr (BUFST) {
+      // the wave's output row is uniform: one buffer store, no branch; lanes
+      // that do not write carry an offset the range check drops
+      uint32_t* row = uniform_ptr(L.out_row);
+      __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc(row, 0, L.D * 4, kBufferDword3);
+      __builtin_amdgcn_raw_buffer_store_b32(x & L.smask, rs, L.soff, 0, 0);
+    } else {
+      if (L.store && i - 2 * TM < L.hl)
+        *(uint32_t*)((char*)L.out_row + L.soff) = x & L.smask;
+    }
     advance_out(L);
   }
 }
 
-template <int TM, bool MASKED, bool ALIGNED, int K>
-__device__ __forceinline__ void prologue(int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[3]) {
+template <int TM, bool MASKED, bool ALIGNED, int PD, bool BUFST, int K>
+__device__ __forceinline__ void prologue(int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[PD]) {
   if constexpr (K < 2 * TM) {
-    step<TM, MASKED, ALIGNED, K % 3, true, K>(K, nsteps, L, P, PF);
-    prologue<TM, MASKED, ALIGNED, K + 1>(nsteps, L, P, PF);
+    step<TM, MASKED, ALIGNED, PD, BUFST, K % 3, K % PD, true, K>(K, nsteps, L, P, PF);
+    prologue<TM, MASKED, ALIGNED, PD, BUFST, K + 1>(nsteps, L, P, PF);
   }
 }
 
-// Sweep one tile: H output rows (the wave's largest band), TM generations.
-template <int TM, bool MASKED, bool ALIGNED>
+// Steady state: PD consecutive steps starting at a step index congruent to
+// 2 TM modulo PD (PD is 3 or 6, so the slot phase is fixed too).
+template <int TM, bool MASKED, bool ALIGNED, int PD, bool BUFST, int U>
+__device__ __forceinline__ void body(int i, int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[PD]) {
+  if constexpr (U < PD) {
+    constexpr int k = 2 * TM + U;
+    step<TM, MASKED, ALIGNED, PD, BUFST, k % 3, k % PD, false, 0>(i + U, nsteps, L, P, PF);
+    body<TM, MASKED, ALIGNED, PD, BUFST, U + 1>(i, nsteps, L, P, PF);
+  }
+}
+
+template <int TM, bool MASKED, bool ALIGNED, int PD, bool BUFST, int U>
+__device__ __forceinline__ void tail(int i, int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[PD]) {
+  if constexpr (U < PD - 1) {
+    if (i + U < nsteps) {
+      constexpr int k = 2 * TM + U;
+      step<TM, MASKED, ALIGNED, PD, BUFST, k % 3, k % PD, false, 0>(i + U, nsteps, L, P, PF);
+      tail<TM, MASKED, ALIGNED, PD, BUFST, U + 1>(i, nsteps, L, P, PF);
+    }
+  }
+}
+
+// Sweep one tile: H output rows (the wave's largest band), TM generations,
+// input rows requested PD steps ahead of use.
+template <int TM, bool MASKED, bool ALIGNED, int PD, bool BUFST>
 __device__ void run_tile(Lane& L, int H) {
   static_assert(TM >= 1 && TM <= kMaxT, "generations per pass");
+  static_assert(PD == 3 || PD == 6, "prefetch distance");
   Pipe<TM> P;
-  Raw PF[3];
+  Raw PF[PD];
   const int nsteps = H + 2 * TM;  // >= 3
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < PD; ++k) {
     PF[k] = load_raw<ALIGNED>(L);
     advance_in(L);
   }
-  prologue<TM, MASKED, ALIGNED, 0>(nsteps, L, P, PF);
-  constexpr int P0 = (2 * TM) % 3, P1 = (2 * TM + 1) % 3, P2 = (2 * TM + 2) % 3;
+  prologue<TM, MASKED, ALIGNED, PD, BUFST, 0>(nsteps, L, P, PF);
   int i = 2 * TM;
-  for (; i + 2 < nsteps; i += 3) {
-    step<TM, MASKED, ALIGNED, P0, false, 0>(i, nsteps, L, P, PF);
-    step<TM, MASKED, ALIGNED, P1, false, 0>(i + 1, nsteps, L, P, PF);
-    step<TM, MASKED, ALIGNED, P2, false, 0>(i + 2, nsteps, L, P, PF);
-  }
-  if (i < nsteps) step<TM, MASKED, ALIGNED, P0, false, 0>(i, nsteps, L, P, PF);
-  if (i + 1 < nsteps) step<TM, MASKED, ALIGNED, P1, false, 0>(i + 1, nsteps, L, P, PF);
+  for (; i + PD - 1 < nsteps; i += PD) body<TM, MASKED, ALIGNED, PD, BUFST, 0>(i, nsteps, L, P, PF);
+  tail<TM, MASKED, ALIGNED, PD, BUFST, 0>(i, nsteps, L, P, PF);
 }
 
 // Workgroups are dealt to the 8 XCDs of the chip in turn; give each XCD a
@@ -310,7 +370,7 @@ struct PassArgs {
   int32_t R, C, D;
 };
 
-template <int TM>
+template <int TM, int PD>
 __global__ __launch_bounds__(64) void k_board_pass(PassArgs a, GridGeom g) {
   const int nitems = g.nstrips * g.nbands;
   const int item = xcd_item(nitems);
@@ -324,10 +384,11 @@ __global__ __launch_bounds__(64) void k_board_pass(PassArgs a, GridGeom g) {
   const int nl = us + 2;
   Lane L;
   lane_setup(L, a.src, a.dst, a.R, a.C, a.D, ds - 1 + lane, lane, nl, rb, hb, TM, TM, lane < nl);
+  if (!L.store) L.soff = kDroppedOffset;
   if ((a.C & 31) == 0)
-    run_tile<TM, false, true>(L, hb);
+    run_tile<TM, false, true, PD, true>(L, hb);
   else
-    run_tile<TM, false, false>(L, hb);
+    run_tile<TM, false, false, PD, true>(L, hb);
 }
 
 // ---------------------------------------------------------------------------
@@ -364,9 +425,9 @@ __global__ __launch_bounds__(64) void k_batch_pass(const BoardDesc* __restrict__
     lane_setup(L, bd.src0, bd.w[0], bd.R, bd.C, bd.D, 0, 0, 1, 0, 1, TM, TM, false);
   }
   if (w.flags & kItemAligned)
-    run_tile<TM, MASKED, true>(L, w.h);
+    run_tile<TM, MASKED, true, 3, false>(L, w.h);
   else
-    run_tile<TM, MASKED, false>(L, w.h);
+    run_tile<TM, MASKED, false, 3, false>(L, w.h);
 }
 
 // ---------------------------------------------------------------------------
@@ -426,22 +487,26 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
 // Host-side launchers (called by the C ABI in gol_capi.cpp).
 // ---------------------------------------------------------------------------
 template <int TM>
-static hipError_t launch_board_pass_t(const PassArgs& a, const GridGeom& g, hipStream_t st) {
+static hipError_t launch_board_pass_t(const PassArgs& a, const GridGeom& g, int pd,
+                                      hipStream_t st) {
   const int nitems = g.nstrips * g.nbands;
   const int grid = ((nitems + 7) / 8) * 8;
-  hipLaunchKernelGGL(k_board_pass<TM>, dim3(grid), dim3(64), 0, st, a, g);
+  if (pd == 6)
+    hipLaunchKernelGGL((k_board_pass<TM, 6>), dim3(grid), dim3(64), 0, st, a, g);
+  else
+    hipLaunchKernelGGL((k_board_pass<TM, 3>), dim3(grid), dim3(64), 0, st, a, g);
   return hipGetLastError();
 }
 
 hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
-                             int32_t D, const GridGeom& g, hipStream_t st) {
+                             int32_t D, const GridGeom& g, int pd, hipStream_t st) {
   PassArgs a{src, dst, R, C, D};
   switch (T) {
-    case 1: return launch_board_pass_t<1>(a, g, st);
-    case 2: return launch_board_pass_t<2>(a, g, st);
-    case 4: return launch_board_pass_t<4>(a, g, st);
-    case 8: return launch_board_pass_t<8>(a, g, st);
-    case 16: return launch_board_pass_t<16>(a, g, st);
+    case 1: return launch_board_pass_t<1>(a, g, pd, st);
+    case 2: return launch_board_pass_t<2>(a, g, pd, st);
+    case 4: return launch_board_pass_t<4>(a, g, pd, st);
+    case 8: return launch_board_pass_t<8>(a, g, pd, st);
+    case 16: return launch_board_pass_t<16>(a, g, pd, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -2,6 +2,7 @@
 #include "gol_plan.h"
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <numeric>
 
@@ -35,17 +36,50 @@ std::vector<int> single_board_passes(int64_t generations, int T) {
   return p;
 }
 
-int default_band_rows(int64_t rows, int64_t cols, int T) {
+// Throughput of the tile pass relative to its best, against resident waves
+// per SIMD (measured on MI355X for 16384^2 and 65536^2 boards after removing
+// the halo-row overhead; the two boards agree): latency is hidden better
+// with more waves.
+static double occupancy_factor(double waves_per_simd) {
+  static const double k[] = {1, 2, 3, 4, 6, 8, 12, 16};
+  static const double f[] = {0.45, 0.68, 0.80, 0.86, 0.90, 0.93, 0.97, 0.97};
+  if (waves_per_simd <= k[0]) return f[0] * waves_per_simd / k[0];
+  for (int i = 1; i < 8; ++i)
+    if (waves_per_simd <= k[i])
+      return f[i - 1] + (f[i] - f[i - 1]) * (waves_per_simd - k[i - 1]) / (k[i] - k[i - 1]);
+  return f[7];
+}
+
+int default_band_rows(int64_t rows, int64_t cols, int T, int nsimd) {
   const int64_t D = dwords_per_row(cols);
   const int64_t ns = (D + kStripDwords - 1) / kStripDwords;
-  // about 2048 tiles (8 waves per compute unit) when the board allows it
-  int64_t h = rows * ns / 2048;
-  const int64_t lo = std::max<int64_t>(16, 4 * T);
-  h = std::max<int64_t>(h, lo);
-  h = std::min<int64_t>(h, 512);
-  h = std::min<int64_t>(h, rows);
-  return (int)std::max<int64_t>(h, 1);
+  if (nsimd < 1) nsimd = 1024;
+  // Candidate band counts put the wave total just under a multiple of the
+  // SIMD count (a SIMD holding one wave more than the rest sets the pace).
+  // Each band sweeps h + 2T rows to emit h; stage s runs from step 2s, so the
+  // pipeline does h + T + 1 row steps of work per T generations of h rows.
+  // Estimated time: waves on the busiest SIMD x row steps per wave, slowed
+  // by the occupancy factor of that many resident waves.
+  double best = 1e300;
+  int64_t best_h = std::min<int64_t>(rows, 64);
+  for (int k : {1, 2, 3, 4, 6, 8, 12, 16, 24}) {
+    const int64_t bands = std::max<int64_t>(1, (int64_t)k * nsimd / ns);
+    const int64_t h = std::max<int64_t>(1, (rows + bands - 1) / bands);
+    if (h > 65535) continue;
+    const int64_t nb = (rows + h - 1) / h;
+    const double waves = (double)(nb * ns);
+    const double per_simd_max = std::ceil(waves / nsimd);
+    const double t = per_simd_max * (double)(h + T + 1) /
+                     occupancy_factor(std::min(per_simd_max, 16.0));
+    if (t < best) {
+      best = t;
+      best_h = h;
+    }
+  }
+  return (int)best_h;
 }
+
+int default_prefetch(int T) { return T >= 16 ? 6 : 3; }
 
 namespace {
 struct ItemBuild {

@@ -61,8 +61,12 @@ bool build_plan(const std::vector<BoardReq>& boards, int T, int band_rows, HostP
                 std::string& err);
 
 // Default band height for the single-board kernel: tall bands amortise the
-// 2T halo rows, but enough tiles are needed to fill 256 compute units.
-int default_band_rows(int64_t rows, int64_t cols, int T);
+// 2T halo rows, but enough waves per SIMD are needed to hide latency, and the
+// wave total should not leave a few SIMDs one wave behind the rest.
+int default_band_rows(int64_t rows, int64_t cols, int T, int nsimd);
+
+// Prefetch distance (rows) of the single-board kernel for T generations per pass.
+int default_prefetch(int T);
 
 bool valid_T(int T);
 

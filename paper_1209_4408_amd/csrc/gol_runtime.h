@@ -26,6 +26,7 @@ void reap_deferred(bool wait);
 int check_board(int64_t rows, int64_t cols, int64_t gens);
 bool ranges_partially_overlap(const void* a, const void* b, size_t bytes);
 int default_T();
+int simd_count();
 
 int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t* d_out,
                 hipStream_t st, int T, int band_rows);
