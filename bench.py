@@ -70,6 +70,21 @@ def cpu_baseline(rows, cols, p, seed, budget_s=12.0):
                       f"{threads} OpenMP threads, byte-per-cell C oracle"}
 
 
+def measured_traffic(record: str):
+    """HBM bytes per launch from the committed counter record (rocprofv3
+    FETCH_SIZE / WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", record)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def roofline_alu(cells, T, avg_launch_s):
     ops = OPS_PER_CELL_UPDATE * cells * T
     achieved = ops / avg_launch_s / 1e12
@@ -127,6 +142,8 @@ def single_board(args, R, C, G, p, label):
     res = {"value": value, "wall_s": wall, "dev_s": dev,
            "roofline": roofline_alu(cells, T, avg_launch) if T > 1 else roofline_hbm(cells,
                                                                                        avg_launch)}
+    if (R, C, T) == (16384, 16384, 8):
+        res["roofline"]["traffic"] = measured_traffic("traffic_k_board_pass_16384x16384.json")
     extra = {}
     if args.compare_t1:
         wall1, dev1 = time_packed(gol, torch, d_in, d_out, R, C, G, max(1, args.steps // 2), 1, 1)
