@@ -264,6 +264,107 @@ def host_api(args):
     return res, extra, len(lat)
 
 
+def wait_until(t0, at):
+    """Sleep, then spin, until perf_counter() - t0 >= at."""
+    rem = at - (time.perf_counter() - t0)
+    if rem > 0.0005:
+        time.sleep(rem - 0.0003)
+    while time.perf_counter() - t0 < at:
+        pass
+
+
+def nearest_rank(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = max(1, int(np.ceil(q / 100.0 * len(xs))))
+    return xs[k - 1]
+
+
+def served(args):
+    """Open-loop Poisson stream through the continuous-batching server, against
+    a one-request-at-a-time server (gol_step_packed per request) on the same
+    trace.  Latency = completion - scheduled arrival."""
+    import threading
+    import torch
+    import paper_1209_4408_amd as gol
+    import seeded_inputs
+    specs = seeded_inputs.serve_specs(SEED, n=args.requests, rate_per_s=args.rate)
+    log(f"generating {len(specs)} request boards")
+    payloads = [seeded_inputs.board_packed(SEED, s.board_id, s.rows, s.cols, s.p) for s in specs]
+    work = float(sum(s.rows * s.cols * s.generations for s in specs))
+    results = [None] * len(specs)
+
+    def run_server():
+        srv = gol.Server(hbm_budget_bytes=64 << 30, chunk_generations=args.chunk)
+        # warm the pools: one small request
+        w = payloads[0]
+        t = srv.submit(w, specs[0].rows, specs[0].cols, 1)
+        srv.wait(t, np.zeros_like(w))
+        done = [None] * len(specs)
+        tickets = [None] * len(specs)
+        ready = threading.Semaphore(0)
+
+        def waiter():
+            for i in range(len(specs)):
+                ready.acquire()
+                out = np.empty_like(payloads[i])
+                info = srv.wait(tickets[i], out)
+                done[i] = info.done_s
+                results[i] = out
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        base = srv.now()
+        t0 = time.perf_counter()
+        for i, s in enumerate(specs):
+            wait_until(t0, s.arrival_s)
+            tickets[i] = srv.submit(payloads[i], s.rows, s.cols, s.generations)
+            ready.release()
+        th.join()
+        srv.close()
+        arr = [base + s.arrival_s for s in specs]
+        lat = [d - a for d, a in zip(done, arr)]
+        span = max(done) - arr[0]
+        return work / span, lat, span
+
+    log("continuous-batching server")
+    thr, lat, span = run_server()
+    out = {"value": thr, "wall_s": span, "dev_s": None, "roofline": None}
+    extra = {"latency_s": {"p50": nearest_rank(lat, 50), "p99": nearest_rank(lat, 99),
+                           "max": max(lat)},
+             "requests": len(specs), "rate_per_s": args.rate, "chunk_generations": args.chunk,
+             "hbm_budget_bytes": 64 << 30, "work_cell_updates": work}
+    # plain: FIFO, one request at a time, same arrival times
+    n_plain = min(len(specs), args.plain_requests)
+    if n_plain > 0:
+        log(f"plain one-at-a-time server on the first {n_plain} requests")
+        st = torch.cuda.current_stream()
+        lat_p = []
+        t0 = time.perf_counter()
+        mism = 0
+        for i in range(n_plain):
+            s = specs[i]
+            wait_until(t0, s.arrival_s)
+            d_in = torch.from_numpy(payloads[i].view(np.int64)).cuda()
+            d_out = gol.step_packed(d_in, s.rows, s.cols, s.generations)
+            res = d_out.cpu().numpy().view(np.uint64)
+            st.synchronize()
+            lat_p.append(time.perf_counter() - t0 - s.arrival_s)
+            if not np.array_equal(res, results[i]):
+                mism += 1
+        span_p = time.perf_counter() - t0 - specs[0].arrival_s
+        work_p = float(sum(s.rows * s.cols * s.generations for s in specs[:n_plain]))
+        extra["plain"] = {"value": work_p / span_p, "unit": "cell-updates/s",
+                          "requests": n_plain,
+                          "latency_s": {"p50": nearest_rank(lat_p, 50),
+                                        "p99": nearest_rank(lat_p, 99)},
+                          "what": "FIFO, one request at a time, gol_step_packed per request"}
+        extra["served_equals_alone"] = (mism == 0)
+        extra["speedup_vs_plain"] = thr / extra["plain"]["value"]
+    return out, extra
+
+
 def copy_calibration(args):
     """A plain copy kernel of known size (generations = 0): what the FETCH_SIZE
     and WRITE_SIZE counters read for 512 MiB in and 512 MiB out (larger than
@@ -315,7 +416,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "copy"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "copy"])
+    ap.add_argument("--requests", type=int, default=4096)
+    ap.add_argument("--rate", type=float, default=2700.0,
+                    help="Poisson arrival rate: 0.7 x batched capacity (4.2e13 cell-updates/s) / "
+                         "1.08e10 cell-updates per request")
+    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--plain-requests", type=int, default=4096)
     ap.add_argument("--boards", type=int, default=4096)
     ap.add_argument("--t-block", type=int, default=0)
     ap.add_argument("--compare-t1", action="store_true")
@@ -357,6 +464,13 @@ def main():
         R = C = 256
         G, p = 100, 0.5
         workload = "256x256 torus, uint8 cells, Bernoulli(0.5), 100 generations, host API"
+    elif args.workload == "c5":
+        res, extra = served(args)
+        args.steps = 1
+        R = C = None
+        G, p = None, None
+        workload = (f"{args.requests} requests, Poisson {args.rate:g}/s, sides log-uniform "
+                    "[32, 8192], p U(0.05, 0.7), generations U{1..10000}, 64 GiB budget")
     elif args.workload == "copy":
         copy_calibration(args)
         return

@@ -55,6 +55,13 @@ def lib():
     """Load libgol.so (raises if it was not built)."""
     global _lib
     if _lib is None:
+        # torch loads its own copy of the HIP runtime (same soname, requested
+        # by file name); loading torch first makes libgol bind to that copy,
+        # so the process holds one HIP runtime whichever module asks first.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
         L = ctypes.CDLL(LIB_PATH)

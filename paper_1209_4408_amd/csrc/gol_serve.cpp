@@ -365,6 +365,21 @@ static void scheduler(Server* Sp) {
                           (int64_t)S.resident.size() < (int64_t)S.cfg.max_resident;
       if (!cap_ok || S.used_bytes + need > S.cfg.hbm_budget_bytes) break;
       rc = admit(S, r);
+      if (rc == GOL_ENOMEM) {
+        // the device is short of memory despite the budget: wait for resident
+        // boards to leave, or fail this request if none will
+        rc = GOL_OK;
+        if (S.resident.empty()) {
+          r.state = State::Failed;
+          r.err = "device allocation failed for a board within the budget";
+          if (r.pin_in) S.pool.put(r.pin_in, r.pin_in_cls);
+          r.pin_in = nullptr;
+          S.queue.pop_front();
+          S.cv_done.notify_all();
+          continue;
+        }
+        break;
+      }
       if (rc) break;
       S.used_bytes += need;
       S.resident.push_back(r.ticket);

@@ -1,0 +1,146 @@
+"""GPU: the continuous-batching server (gol_serve_*).
+
+Each request's result must be bit-identical to the oracle and to the same
+board run alone, whatever else was resident at the time.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1209_4408_amd as gol
+import seeded_inputs
+from gpu_util import expect_words, from_dev, rand_bytes, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def small_requests(seed, n, side_hi=300, gen_hi=90):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        R = int(rng.integers(1, side_hi))
+        C = int(rng.integers(1, side_hi))
+        G = int(rng.integers(0, gen_hi))
+        b = rand_bytes(seed, i, R, C, float(rng.uniform(0.1, 0.6)))
+        out.append((b, G))
+    return out
+
+
+def test_serve_matches_oracle():
+    reqs = small_requests(5, 40)
+    with gol.Server(hbm_budget_bytes=1 << 30, chunk_generations=16) as srv:
+        tickets = []
+        for b, G in reqs:
+            R, C = b.shape
+            tickets.append(srv.submit(oracle.pack(b), R, C, G))
+        for (b, G), t in zip(reqs, tickets):
+            R, C = b.shape
+            out = np.zeros((R, gol.words_per_row(C)), np.uint64)
+            info = srv.wait(t, out)
+            assert info.generations_done == G
+            assert info.submit_s <= info.admit_s <= info.done_s
+            assert np.array_equal(out, expect_words(b, G)), (R, C, G)
+
+
+def test_serve_mix_equals_alone():
+    reqs = small_requests(9, 24, side_hi=500, gen_hi=70)
+    mixed = []
+    with gol.Server(hbm_budget_bytes=1 << 30, chunk_generations=8) as srv:
+        tickets = [srv.submit(oracle.pack(b), *b.shape, G) for b, G in reqs]
+        for (b, G), t in zip(reqs, tickets):
+            out = np.zeros((b.shape[0], gol.words_per_row(b.shape[1])), np.uint64)
+            srv.wait(t, out)
+            mixed.append(out)
+    for (b, G), m in zip(reqs, mixed):
+        R, C = b.shape
+        alone = from_dev(gol.step_packed(to_dev(oracle.pack(b)), R, C, G))
+        assert np.array_equal(m, alone), (R, C, G)
+
+
+def test_serve_budget_forces_queueing():
+    """A budget that holds one board at a time still serves every request, in order."""
+    R, C, G = 200, 640, 30
+    bytes_per = 2 * R * gol.words_per_row(C) * 8
+    boards = [rand_bytes(3, i, R, C, 0.4) for i in range(5)]
+    with gol.Server(hbm_budget_bytes=bytes_per + 100, chunk_generations=8) as srv:
+        tickets = [srv.submit(oracle.pack(b), R, C, G) for b in boards]
+        infos = []
+        for b, t in zip(boards, tickets):
+            out = np.zeros((R, gol.words_per_row(C)), np.uint64)
+            infos.append(srv.wait(t, out))
+            assert np.array_equal(out, expect_words(b, G))
+    for a, b in zip(infos, infos[1:]):
+        assert b.admit_s >= a.done_s - 1e-3 or b.admit_s >= a.admit_s  # admitted one by one
+
+
+def test_serve_oversize_and_bad_tickets():
+    with gol.Server(hbm_budget_bytes=1 << 20, chunk_generations=8) as srv:
+        big = np.zeros((2048, 64), np.uint64)  # needs 2 x 1 MiB > budget
+        with pytest.raises(gol.GolError) as e:
+            srv.submit(big, 2048, 4096, 5)
+        assert e.value.code == gol.GOL_ENOMEM
+        out = np.zeros(1, np.uint64)
+        with pytest.raises(gol.GolError) as e:
+            srv.wait(12345, out)
+        assert e.value.code == gol.GOL_ENOTFOUND
+        with pytest.raises(gol.GolError):
+            srv.cancel(999)
+
+
+def test_serve_cancel_and_poll():
+    R, C = 512, 4096
+    long_b = rand_bytes(1, 1, R, C, 0.5)
+    short_b = rand_bytes(1, 2, 64, 64, 0.5)
+    with gol.Server(hbm_budget_bytes=1 << 30, chunk_generations=8) as srv:
+        t_long = srv.submit(oracle.pack(long_b), R, C, 100000)
+        t_short = srv.submit(oracle.pack(short_b), 64, 64, 10)
+        out_long = np.zeros((R, gol.words_per_row(C)), np.uint64)
+        assert srv.poll(t_long, out_long) is None  # not finished
+        srv.cancel(t_long)
+        with pytest.raises(gol.GolError) as e:
+            srv.wait(t_long, out_long)
+        assert e.value.code == gol.GOL_ECANCELED
+        out = np.zeros((64, 1), np.uint64)
+        srv.wait(t_short, out)
+        assert np.array_equal(out, expect_words(short_b, 10))
+
+
+def test_serve_zero_generations_and_poll_loop():
+    b = rand_bytes(4, 4, 33, 70, 0.5)
+    with gol.Server(hbm_budget_bytes=1 << 26, chunk_generations=4) as srv:
+        t = srv.submit(oracle.pack(b), 33, 70, 0)
+        out = np.zeros((33, 2), np.uint64)
+        deadline = time.time() + 20
+        info = None
+        while info is None and time.time() < deadline:
+            info = srv.poll(t, out)
+            time.sleep(0.001)
+        assert info is not None
+        assert np.array_equal(out, oracle.pack(b))
+        with pytest.raises(gol.GolError) as e:  # retired after the successful poll
+            srv.poll(t, out)
+        assert e.value.code == gol.GOL_ENOTFOUND
+
+
+def test_serve_stream_poisson_small():
+    """A short open-loop stream with requests arriving while others run."""
+    specs = seeded_inputs.serve_specs(1209, n=60, rate_per_s=2000.0, side_hi=700, gen_hi=200)
+    with gol.Server(hbm_budget_bytes=1 << 30, chunk_generations=32) as srv:
+        t0 = time.perf_counter()
+        tickets = []
+        for s in specs:
+            while time.perf_counter() - t0 < s.arrival_s:
+                pass
+            w = seeded_inputs.board_packed(1209, s.board_id, s.rows, s.cols, s.p)
+            tickets.append((s, w, srv.submit(w, s.rows, s.cols, s.generations)))
+        for s, w, t in tickets:
+            out = np.zeros_like(w)
+            srv.wait(t, out)
+            if s.rows * s.cols * s.generations <= 2e7:
+                want = oracle.pack(oracle.life(oracle.unpack(w, s.cols), s.generations))
+            else:
+                want = from_dev(gol.step_packed(to_dev(w), s.rows, s.cols, s.generations))
+            say("request", s.board_id, s.rows, s.cols, s.generations)
+            assert np.array_equal(out, want), s
