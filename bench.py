@@ -70,10 +70,11 @@ def cpu_baseline(rows, cols, p, seed, budget_s=12.0):
                       f"{threads} OpenMP threads, byte-per-cell C oracle"}
 
 
-def measured_traffic(record: str):
+def measured_traffic(record: str, band_rows=None):
     """HBM bytes per launch from the committed counter record (rocprofv3
     FETCH_SIZE / WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when the kernel source has changed since the counters were taken."""
+    when there is none for this kernel and tiling, or the kernel source has
+    changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
@@ -82,16 +83,19 @@ def measured_traffic(record: str):
     src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
         return None
+    if band_rows is not None and rec.get("band_rows") not in (None, band_rows):
+        return None
     return rec["hbm_bytes_per_launch"]
 
 
 def roofline_alu(cells, T, avg_launch_s):
     ops = OPS_PER_CELL_UPDATE * cells * T
+    pd = 6 if T >= 16 else 3
     achieved = ops / avg_launch_s / 1e12
     peak = VALU_PEAK_OPS / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
             "frac": achieved / peak, "traffic": None,
-            "kernel": f"k_board_pass<{T}>", "avg_launch_us": avg_launch_s * 1e6,
+            "kernel": f"k_board_pass<{T}, {pd}>", "avg_launch_us": avg_launch_s * 1e6,
             "ops_per_launch": ops}
 
 
@@ -100,7 +104,7 @@ def roofline_hbm(cells, avg_launch_s):
     achieved = by / avg_launch_s / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
             "frac": achieved / (HBM_PEAK_BYTES / 1e9), "traffic": None,
-            "kernel": "k_board_pass<1>", "avg_launch_us": avg_launch_s * 1e6,
+            "kernel": "k_board_pass<1, 3>", "avg_launch_us": avg_launch_s * 1e6,
             "bytes_per_launch": by}
 
 
@@ -126,24 +130,34 @@ def single_board(args, R, C, G, p, label):
     import paper_1209_4408_amd as gol
     import seeded_inputs
     from paper_1209_4408_amd import build as _b  # noqa: F401
-    T = args.t_block or 8
     log(f"generating {R}x{C} board p={p}")
     w = seeded_inputs.board_packed(SEED, 0, R, C, p)
     d_in = torch.from_numpy(w.view(np.int64)).cuda()
     del w
     d_out = torch.empty_like(d_in)
     torch.cuda.synchronize()
+    band = None
+    if args.t_block:
+        T = args.t_block
+    elif args.no_tune:
+        T = 8
+    else:
+        # one-off autotuning of (T, band height) for this size, before timing
+        T, band = gol.tune(R, C)
+        log(f"autotuned: T={T} band_rows={band}")
+    args.tuned = {"t_block": T, "band_rows": band}
     log(f"timing {args.steps} steps after {args.warmup} warmup, T={T}")
     wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, args.steps, args.warmup, T)
     cells = R * C
     value = cells * G * args.steps / wall
-    launches = G // T
-    avg_launch = dev / (args.steps * launches)
+    # average duration of one T-generation pass: device time per generation x T
+    # (a run of G = 1000 at T = 16 also holds one 8-generation pass)
+    avg_launch = dev / (args.steps * G) * T
     res = {"value": value, "wall_s": wall, "dev_s": dev,
            "roofline": roofline_alu(cells, T, avg_launch) if T > 1 else roofline_hbm(cells,
                                                                                        avg_launch)}
-    if (R, C, T) == (16384, 16384, 8):
-        res["roofline"]["traffic"] = measured_traffic("traffic_k_board_pass_16384x16384.json")
+    rec = f"traffic_k_board_pass{T}_{R}x{C}.json"
+    res["roofline"]["traffic"] = measured_traffic(rec, band)
     extra = {}
     if args.compare_t1:
         wall1, dev1 = time_packed(gol, torch, d_in, d_out, R, C, G, max(1, args.steps // 2), 1, 1)
@@ -322,19 +336,20 @@ def served(args):
             tickets[i] = srv.submit(payloads[i], s.rows, s.cols, s.generations)
             ready.release()
         th.join()
+        stats = srv.stats()
         srv.close()
         arr = [base + s.arrival_s for s in specs]
         lat = [d - a for d, a in zip(done, arr)]
         span = max(done) - arr[0]
-        return work / span, lat, span
+        return work / span, lat, span, stats
 
     log("continuous-batching server")
-    thr, lat, span = run_server()
+    thr, lat, span, stats = run_server()
     out = {"value": thr, "wall_s": span, "dev_s": None, "roofline": None}
     extra = {"latency_s": {"p50": nearest_rank(lat, 50), "p99": nearest_rank(lat, 99),
                            "max": max(lat)},
              "requests": len(specs), "rate_per_s": args.rate, "chunk_generations": args.chunk,
-             "hbm_budget_bytes": 64 << 30, "work_cell_updates": work}
+             "hbm_budget_bytes": 64 << 30, "work_cell_updates": work, "server": stats}
     # plain: FIFO, one request at a time, same arrival times
     n_plain = min(len(specs), args.plain_requests)
     if n_plain > 0:
@@ -421,12 +436,13 @@ def main():
     ap.add_argument("--rate", type=float, default=2700.0,
                     help="Poisson arrival rate: 0.7 x batched capacity (4.2e13 cell-updates/s) / "
                          "1.08e10 cell-updates per request")
-    ap.add_argument("--chunk", type=int, default=64)
+    ap.add_argument("--chunk", type=int, default=256)
     ap.add_argument("--plain-requests", type=int, default=4096)
     ap.add_argument("--boards", type=int, default=4096)
     ap.add_argument("--t-block", type=int, default=0)
     ap.add_argument("--compare-t1", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (T = 8, model band)")
     ap.add_argument("--sweep", action="store_true",
                     help="time T in {2,4,8,16} x band heights for the single-board workload")
     args = ap.parse_args()
@@ -489,7 +505,10 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": workload, "rows": R, "cols": C, "generations": G, "p": p,
-                   "seed": SEED, "t_block": args.t_block or 8, "parallelism": "single GPU"},
+                   "seed": SEED, "t_block": getattr(args, "tuned", {}).get("t_block",
+                                                                          args.t_block or 8),
+                   "band_rows": getattr(args, "tuned", {}).get("band_rows"),
+                   "parallelism": "single GPU"},
         "roofline": res["roofline"],
     }
     line.update(extra)

@@ -80,6 +80,19 @@ int gol_step_packed(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t ge
 int gol_step_packed_ex(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t generations,
                        uint64_t* d_out, void* stream, int t_block);
 
+/*
+ * Autotuner of the single-board path: times candidate (generations per pass,
+ * band height) pairs for rows x cols boards on the current device, using two
+ * scratch boards of that size from the stream-ordered pool (the pass's run
+ * time does not depend on the cells), and remembers the fastest per
+ * generation.  Later gol_step_packed / gol_step_packed_ex calls with
+ * t_block = 0 on this device and size use it.  Synchronous on `stream`
+ * (tens of milliseconds).  out_t_block / out_band_rows may be NULL.  If the
+ * environment variable GOL_AUTOTUNE_CACHE names a file, choices are appended
+ * to it and read back by later processes.
+ */
+int gol_tune(int64_t rows, int64_t cols, void* stream, int* out_t_block, int* out_band_rows);
+
 /* Device conversions between the byte and packed layouts (asynchronous). */
 int gol_pack(const uint8_t* d_bytes, int64_t rows, int64_t cols, uint64_t* d_packed,
              void* stream);
@@ -150,6 +163,20 @@ int gol_serve_wait(gol_server* srv, uint64_t ticket, uint64_t* host_out, gol_req
 int gol_serve_cancel(gol_server* srv, uint64_t ticket);
 /* Seconds on the server's clock (the time base of gol_request_info). */
 double gol_serve_now(const gol_server* srv);
+
+/* Counters since the server was created (thread-safe snapshot). */
+typedef struct {
+  int64_t chunks;          /* chunks queued (one batched schedule each) */
+  int64_t launches;        /* tile-pass launches queued */
+  int64_t admitted;        /* requests admitted to the device */
+  int64_t retired;         /* requests whose result copy was queued */
+  double plan_host_s;      /* host seconds spent building chunk schedules */
+  double device_busy_s;    /* device seconds of completed chunks (first to last launch) */
+  double cell_updates;     /* cell updates queued */
+  int64_t max_resident;    /* largest number of boards in one chunk */
+  double mean_resident;    /* boards per chunk, averaged over chunks */
+} gol_serve_stats;
+int gol_serve_get_stats(const gol_server* srv, gol_serve_stats* out);
 int gol_serve_destroy(gol_server* srv);
 
 /*

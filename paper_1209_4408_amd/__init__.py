@@ -46,6 +46,14 @@ class ServeConfig(ctypes.Structure):
                 ("t_block", ctypes.c_int32)]
 
 
+class ServeStats(ctypes.Structure):
+    _fields_ = [("chunks", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("admitted", ctypes.c_int64), ("retired", ctypes.c_int64),
+                ("plan_host_s", ctypes.c_double), ("device_busy_s", ctypes.c_double),
+                ("cell_updates", ctypes.c_double), ("max_resident", ctypes.c_int64),
+                ("mean_resident", ctypes.c_double)]
+
+
 class RequestInfo(ctypes.Structure):
     _fields_ = [("generations_done", ctypes.c_int64), ("submit_s", ctypes.c_double),
                 ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
@@ -72,6 +80,7 @@ def lib():
             "gol_step": (c_int, [vp, i64, i64, i64, vp]),
             "gol_step_packed": (c_int, [vp, i64, i64, i64, vp, vp]),
             "gol_step_packed_ex": (c_int, [vp, i64, i64, i64, vp, vp, c_int]),
+            "gol_tune": (c_int, [i64, i64, vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
             "gol_pack": (c_int, [vp, i64, i64, vp, vp]),
             "gol_unpack": (c_int, [vp, i64, i64, vp, vp]),
             "gol_batch_run": (c_int, [vp, i64, vp]),
@@ -86,6 +95,7 @@ def lib():
             "gol_serve_wait": (c_int, [vp, ctypes.c_uint64, vp, ctypes.POINTER(RequestInfo)]),
             "gol_serve_cancel": (c_int, [vp, ctypes.c_uint64]),
             "gol_serve_now": (ctypes.c_double, [vp]),
+            "gol_serve_get_stats": (c_int, [vp, ctypes.POINTER(ServeStats)]),
             "gol_serve_destroy": (c_int, [vp]),
             "gol_set_allocator": (c_int, [vp, vp, vp]),
             "gol_debug_plan_tables": (c_int, [vp, vp, vp, i64, c_int, c_int, vp, i64, vp, i64, vp,
@@ -155,6 +165,13 @@ def step_packed(d_in, rows: int, cols: int, generations: int, d_out=None, stream
     _check(lib().gol_step_packed_ex(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
                                     _stream_handle(stream), int(t_block)))
     return d_out
+
+
+def tune(rows: int, cols: int, stream=None) -> tuple[int, int]:
+    """Autotune the single-board path for this size; returns (t_block, band_rows)."""
+    t, h = ctypes.c_int(), ctypes.c_int()
+    _check(lib().gol_tune(rows, cols, _stream_handle(stream), ctypes.byref(t), ctypes.byref(h)))
+    return t.value, h.value
 
 
 def pack(d_bytes, rows: int, cols: int, d_out=None, stream=None):
@@ -268,6 +285,11 @@ class Server:
 
     def now(self) -> float:
         return float(lib().gol_serve_now(self._h))
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        _check(lib().gol_serve_get_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServeStats._fields_}
 
     def close(self) -> None:
         if self._h:

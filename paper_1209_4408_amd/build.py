@@ -19,7 +19,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall",
 # Device code: gfx950 only; keep the compiler from forming packed-FP32 ops.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
-HOST_SOURCES = ["gol_capi.cpp", "gol_plan.cpp", "gol_serve.cpp"]
+HOST_SOURCES = ["gol_capi.cpp", "gol_plan.cpp", "gol_serve.cpp", "gol_tune.cpp"]
 DEVICE_SOURCES = ["gol_kernels.hip"]
 
 

@@ -167,6 +167,9 @@ bool ranges_partially_overlap(const void* a, const void* b, size_t bytes) {
 
 int default_T() { return 8; }
 
+// Band height of batched schedules (tiles of many boards share a level).
+constexpr int kBatchBandRows = 64;
+
 // SIMDs of the current device (4 per compute unit), cached per device.
 int simd_count() {
   static std::mutex mu;
@@ -193,8 +196,14 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
   int rc = check_board(R, C, G);
   if (rc) return rc;
   if (!d_in || !d_out) return set_error(GOL_EINVAL, "null board pointer");
-  if (T == 0) T = default_T();
-  if (!valid_T(T)) return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8 or 16 (got %d)", T);
+  if (T != 0 && !valid_T(T))
+    return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8 or 16 (got %d)", T);
+  // t_block 0: the autotuner's choice for this size if gol_tune ran, else the
+  // default T with the occupancy model's band height
+  TuneChoice tc{0, 0};
+  const bool tuned = tuned_choice(R, C, &tc);
+  if (T == 0) T = tuned ? tc.T : default_T();
+  if (band_rows <= 0 && tuned && tc.T == T) band_rows = tc.band_rows;
   const int64_t W = (C + 63) / 64, D = 2 * W;
   const size_t bytes = (size_t)(R * W * 8);
   if (ranges_partially_overlap(d_in, d_out, bytes))
@@ -335,8 +344,12 @@ int plan_boards(const gol_board* boards, int64_t n, int T, int band_rows, Device
   }
   P.scratch_words = off;
   std::string err;
-  if (!build_plan(req, T, band_rows > 0 ? band_rows : 64, P.hp, err))
-    return set_error(GOL_EINVAL, "%s", err.c_str());
+  if (band_rows <= 0) {
+    band_rows = kBatchBandRows;
+    const char* e = getenv("GOL_BATCH_BAND_ROWS");  // tuning override
+    if (e && atoi(e) > 0) band_rows = atoi(e);
+  }
+  if (!build_plan(req, T, band_rows, P.hp, err)) return set_error(GOL_EINVAL, "%s", err.c_str());
   return GOL_OK;
 }
 

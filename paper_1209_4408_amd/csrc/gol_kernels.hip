@@ -37,6 +37,10 @@
 #ifndef GOL_PREFETCH_FENCE_MASK
 #define GOL_PREFETCH_FENCE_MASK 0
 #endif
+// Prefetch distance (rows) of the batch kernel.
+#ifndef GOL_BATCH_PREFETCH
+#define GOL_BATCH_PREFETCH 3
+#endif
 
 namespace gol {
 
@@ -425,9 +429,9 @@ __global__ __launch_bounds__(64) void k_batch_pass(const BoardDesc* __restrict__
     lane_setup(L, bd.src0, bd.w[0], bd.R, bd.C, bd.D, 0, 0, 1, 0, 1, TM, TM, false);
   }
   if (w.flags & kItemAligned)
-    run_tile<TM, MASKED, true, 3, false>(L, w.h);
+    run_tile<TM, MASKED, true, GOL_BATCH_PREFETCH, false>(L, w.h);
   else
-    run_tile<TM, MASKED, false, 3, false>(L, w.h);
+    run_tile<TM, MASKED, false, GOL_BATCH_PREFETCH, false>(L, w.h);
 }
 
 // ---------------------------------------------------------------------------

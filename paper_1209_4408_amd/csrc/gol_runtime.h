@@ -28,6 +28,13 @@ bool ranges_partially_overlap(const void* a, const void* b, size_t bytes);
 int default_T();
 int simd_count();
 
+// Tuned (generations per pass, band height) for a board size.
+struct TuneChoice {
+  int T;
+  int band_rows;
+};
+bool tuned_choice(int64_t rows, int64_t cols, TuneChoice* out);
+
 int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t* d_out,
                 hipStream_t st, int T, int band_rows);
 

@@ -125,6 +125,8 @@ struct Server {
   // owned by the scheduler thread
   std::vector<PendingFree> pend_free;
   std::deque<hipEvent_t> chunk_events;
+  std::deque<hipEvent_t> chunk_starts;  // timing events, paired with chunk_events
+  gol_serve_stats stats{};
   std::thread th;
 
   double now() const {
@@ -171,7 +173,12 @@ static void reap(Server& S) {
   }
   S.pend_free.resize(k);
   while (!S.chunk_events.empty() && hipEventQuery(S.chunk_events.front()) == hipSuccess) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, S.chunk_starts.front(), S.chunk_events.front()) == hipSuccess)
+      S.stats.device_busy_s += ms * 1e-3;
+    (void)hipEventDestroy(S.chunk_starts.front());
     (void)hipEventDestroy(S.chunk_events.front());
+    S.chunk_starts.pop_front();
     S.chunk_events.pop_front();
   }
 }
@@ -214,6 +221,7 @@ static int admit(Server& S, Request& r) {
   r.pin_in = nullptr;
   r.state = State::Resident;
   r.t_admit = S.now();
+  S.stats.admitted += 1;
   return GOL_OK;
 }
 
@@ -225,6 +233,7 @@ static int queue_chunk(Server& S, std::vector<uint64_t>& retire_now) {
     if (!r.cancel && !r.retiring && r.queued_gens < r.gens) act.push_back(&r);
   }
   if (act.empty()) return GOL_OK;
+  const auto t_plan0 = std::chrono::steady_clock::now();
   const int T = S.cfg.t_block ? S.cfg.t_block : default_T();
   std::vector<BoardReq> req;
   req.reserve(act.size());
@@ -259,12 +268,19 @@ static int queue_chunk(Server& S, std::vector<uint64_t>& retire_now) {
   memcpy(pin, bd.data(), bd.size() * sizeof(BoardDesc));
   memcpy(pin + os, hp.segs.data(), hp.segs.size() * sizeof(Segment));
   memcpy(pin + oi, hp.items.data(), hp.items.size() * sizeof(WaveItem));
+  S.stats.plan_host_s +=
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_plan0).count();
   void* meta = nullptr;
   hipError_t e = hipMallocAsync(&meta, mb, S.compute);
   if (e != hipSuccess) {
     S.pool.put(pin, cls);
     return set_error(GOL_ENOMEM, "server: chunk tables: %s", hipGetErrorString(e));
   }
+  hipEvent_t ev0;
+  e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventRecord(ev0, S.compute);
+  if (e != hipSuccess) return hip_error(e, "server: chunk start event");
+  S.chunk_starts.push_back(ev0);
   e = hipMemcpyAsync(meta, pin, mb, hipMemcpyHostToDevice, S.compute);
   const BoardDesc* d_b = (const BoardDesc*)meta;
   const Segment* d_s = (const Segment*)((char*)meta + os);
@@ -276,10 +292,15 @@ static int queue_chunk(Server& S, std::vector<uint64_t>& retire_now) {
   if (!defer_pinned(S, S.compute, pin, cls) && e == hipSuccess) e = hipErrorUnknown;
   if (e != hipSuccess) return hip_error(e, "server: chunk launch");
   hipEvent_t ev;
-  e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  e = hipEventCreate(&ev);
   if (e == hipSuccess) e = hipEventRecord(ev, S.compute);
   if (e != hipSuccess) return hip_error(e, "server: chunk event");
   S.chunk_events.push_back(ev);
+  S.stats.chunks += 1;
+  S.stats.launches += (int64_t)hp.level_items.size();
+  S.stats.cell_updates += hp.cell_updates;
+  S.stats.max_resident = std::max<int64_t>(S.stats.max_resident, (int64_t)act.size());
+  S.stats.mean_resident += ((double)act.size() - S.stats.mean_resident) / (double)S.stats.chunks;
   for (size_t b = 0; b < act.size(); ++b) {
     Request& r = *act[b];
     r.queued_gens += req[b].generations;
@@ -304,6 +325,7 @@ static int queue_retire(Server& S, Request& r) {
   r.d_buf[0] = r.d_buf[1] = nullptr;
   S.used_bytes -= 2 * r.bytes;
   r.retiring = true;
+  S.stats.retired += 1;
   if (e != hipSuccess) return hip_error(e, "server: result copy");
   return GOL_OK;
 }
@@ -600,6 +622,14 @@ int gol_serve_cancel(gol_server* srv, uint64_t ticket) {
 
 double gol_serve_now(const gol_server* srv) { return srv ? srv->S.now() : 0.0; }
 
+int gol_serve_get_stats(const gol_server* srv, gol_serve_stats* out) {
+  if (!srv || !out) return set_error(GOL_EINVAL, "null argument");
+  Server& S = const_cast<gol_server*>(srv)->S;
+  std::lock_guard<std::mutex> lk(S.mu);
+  *out = S.stats;
+  return GOL_OK;
+}
+
 int gol_serve_destroy(gol_server* srv) {
   if (!srv) return GOL_OK;
   Server& S = srv->S;
@@ -627,6 +657,7 @@ int gol_serve_destroy(gol_server* srv) {
   }
   (void)hipStreamSynchronize(S.copy);
   for (hipEvent_t ev : S.chunk_events) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : S.chunk_starts) (void)hipEventDestroy(ev);
   (void)hipStreamDestroy(S.compute);
   (void)hipStreamDestroy(S.copy);
   delete srv;

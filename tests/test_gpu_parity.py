@@ -144,3 +144,11 @@ def test_tiling_periodicity_on_gpu():
     say("tiled", R, C)
     got = oracle.unpack(run_packed(big, 33), C)
     assert np.array_equal(got, np.tile(oracle.life(x, 33), (7, 5)))
+
+
+def test_autotuned_choice_is_used_and_exact():
+    R, C, G = 700, 3000, 37
+    T, band = gol.tune(R, C)
+    assert T in (4, 8, 16) and 1 <= band <= R
+    b = rand_bytes(77, 1, R, C, 0.4)
+    check(b, G, 0)  # t_block 0 takes the tuned choice
