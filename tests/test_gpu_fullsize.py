@@ -24,6 +24,34 @@ THREADS = max(1, int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
 SEED = 1209
 
 
+def tuner_candidates(R, C):
+    """The (T, band height) pairs gol_tune times for an R x C board."""
+    import torch
+    nsimd = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    D = 2 * ((C + 63) // 64)
+    ns = (D + 61) // 62
+    out = []
+    for T in (4, 8, 16):
+        hs = set()
+        for k in (2, 3, 4, 6, 8, 12, 16):
+            bands = max(1, k * nsimd // ns)
+            hs.add(max(1, -(-R // bands)))
+        out += [(T, h) for h in sorted(hs)]
+    return out
+
+
+def all_candidates_agree(d_in, R, C, G, want):
+    """Every configuration the autotuner can pick gives the same board."""
+    for T, h in tuner_candidates(R, C):
+        os.environ["GOL_BAND_ROWS"] = str(h)
+        try:
+            say(f"  candidate T={T} band={h}")
+            got = from_dev(gol.step_packed(d_in, R, C, G, t_block=T))
+        finally:
+            os.environ.pop("GOL_BAND_ROWS", None)
+        assert np.array_equal(got, want), (T, h)
+
+
 def windows_ok(out_words, in_words, cols, G, spots, k):
     for r0, c0 in spots:
         got = oracle.torus_window_packed(out_words, cols, r0, c0, k, k)
@@ -33,15 +61,19 @@ def windows_ok(out_words, in_words, cols, G, spots, k):
 
 
 def test_16384_board_1000_generations_windows():
-    """The benchmark's default workload: 16384^2, p = 0.3, 1000 generations, default T."""
+    """The benchmark's default workload: 16384^2, p = 0.3, 1000 generations, in the
+    autotuned configuration bench.py times; every other tuner candidate agrees."""
     R = C = 16384
     G = 1000
     w = seeded_inputs.board_packed(SEED, 0, R, C, 0.3)
-    say("16384^2 x 1000 on the GPU")
-    out = from_dev(gol.step_packed(to_dev(w), R, C, G))
+    d_in = to_dev(w)
+    T, band = gol.tune(R, C)
+    say(f"16384^2 x 1000 on the GPU, tuned T={T} band={band}")
+    out = from_dev(gol.step_packed(d_in, R, C, G))
     assert oracle.padding_is_zero(out, C)
     spots = [(R - 6, C - 6), (R - 5, 7000), (9001, C - 4), (4321, 12345)]
     windows_ok(out, w, C, G, spots, 12)
+    all_candidates_agree(d_in, R, C, G, out)
 
 
 def test_16384_board_tiled_every_cell():
@@ -60,10 +92,12 @@ def c3_runs():
     G = 200
     w = seeded_inputs.board_packed(SEED, 0, R, C, 0.5)
     d_in = to_dev(w)
-    say("65536^2 x 200, temporal-blocked")
+    T, band = gol.tune(R, C)
+    say(f"65536^2 x 200, temporal-blocked, tuned T={T} band={band}")
     tb = from_dev(gol.step_packed(d_in, R, C, G))
     say("65536^2 x 200, one generation per launch")
     t1 = from_dev(gol.step_packed(d_in, R, C, G, t_block=1))
+    all_candidates_agree(d_in, R, C, G, tb)
     del d_in
     return w, tb, t1
 
@@ -144,7 +178,7 @@ def test_served_stream_sampled():
     work = np.array([s.rows * s.cols * s.generations for s in specs], dtype=np.float64)
     sample |= set(int(x) for x in np.argsort(work)[:8])
     payloads = {}
-    with gol.Server(hbm_budget_bytes=64 << 30, chunk_generations=64) as srv:
+    with gol.Server(hbm_budget_bytes=64 << 30, chunk_generations=256) as srv:
         tickets = []
         t0 = time.perf_counter()
         for s in specs:
