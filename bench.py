@@ -389,10 +389,17 @@ def copy_calibration(args):
     R = C = 65536
     d_in = torch.zeros((R, C // 64), dtype=torch.int64, device="cuda")
     d_out = torch.empty_like(d_in)
+    gol.step_packed(d_in, R, C, 0, d_out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(args.steps):
         gol.step_packed(d_in, R, C, 0, d_out)
+    e1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_each_way": R * C // 8, "launches": args.steps}), flush=True)
+    dt = e0.elapsed_time(e1) / 1e3 / args.steps
+    print(json.dumps({"copy_bytes_each_way": R * C // 8, "launches": args.steps + 1,
+                      "read_plus_write_GBps": 2 * R * C / 8 / dt / 1e9}), flush=True)
 
 
 def sweep(args):
