@@ -134,7 +134,7 @@ int gol_plan_destroy(gol_plan* plan);
  * `chunk_generations` in one batched schedule, new arrivals join at the next
  * tick, finished boards are copied back and leave.
  */
-typedef struct {
+typedef struct gol_serve_config {
   uint64_t hbm_budget_bytes;   /* device bytes for resident boards */
   int32_t chunk_generations;   /* generations per tick (>= 1) */
   int32_t device;              /* HIP device ordinal */
@@ -175,6 +175,8 @@ typedef struct {
   double cell_updates;     /* cell updates queued */
   int64_t max_resident;    /* largest number of boards in one chunk */
   double mean_resident;    /* boards per chunk, averaged over chunks */
+  int64_t resident_bytes;  /* device bytes of resident boards now */
+  int64_t peak_resident_bytes; /* largest value of resident_bytes (never above the budget) */
 } gol_serve_stats;
 int gol_serve_get_stats(const gol_server* srv, gol_serve_stats* out);
 int gol_serve_destroy(gol_server* srv);

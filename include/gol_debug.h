@@ -32,6 +32,24 @@ int gol_debug_plan_tables(const int64_t* rows, const int64_t* cols, const int64_
                           int64_t cap_items, int32_t* level_items, int64_t cap_levels,
                           int64_t* nsegs, int64_t* nitems, int64_t* nlevels);
 
+/*
+ * A server whose "device" is host memory, for testing the serving scheduler
+ * (admission by budget, chunking, the buffer that holds each board's state,
+ * retirement, cancellation, failure handling) without a GPU.  Every queued
+ * operation completes at once.  Its stand-in for advancing a board by g
+ * generations adds g (mod 2^64) to every word; it computes nothing of the Life
+ * rule.  fail_at_chunk > 0 makes the fail_at_chunk-th chunk report
+ * GOL_EDEVICE (the server then fails every unfinished request).  Use the
+ * gol_serve_* calls on the result; cfg->device is ignored.
+ */
+typedef struct gol_server gol_server;
+typedef struct gol_serve_config gol_serve_config;
+int gol_debug_serve_create_host(const gol_serve_config* cfg, int64_t fail_at_chunk,
+                                gol_server** out);
+/* Largest number of board bytes the host executor held at once (-1 if srv is
+ * not a host-executor server). */
+int64_t gol_debug_serve_host_peak_bytes(const gol_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

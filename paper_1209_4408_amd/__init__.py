@@ -51,7 +51,8 @@ class ServeStats(ctypes.Structure):
                 ("admitted", ctypes.c_int64), ("retired", ctypes.c_int64),
                 ("plan_host_s", ctypes.c_double), ("device_busy_s", ctypes.c_double),
                 ("cell_updates", ctypes.c_double), ("max_resident", ctypes.c_int64),
-                ("mean_resident", ctypes.c_double)]
+                ("mean_resident", ctypes.c_double), ("resident_bytes", ctypes.c_int64),
+                ("peak_resident_bytes", ctypes.c_int64)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -98,6 +99,9 @@ def lib():
             "gol_serve_get_stats": (c_int, [vp, ctypes.POINTER(ServeStats)]),
             "gol_serve_destroy": (c_int, [vp]),
             "gol_set_allocator": (c_int, [vp, vp, vp]),
+            "gol_debug_serve_create_host": (c_int, [ctypes.POINTER(ServeConfig), i64,
+                                                    ctypes.POINTER(vp)]),
+            "gol_debug_serve_host_peak_bytes": (i64, [vp]),
             "gol_debug_plan_tables": (c_int, [vp, vp, vp, i64, c_int, c_int, vp, i64, vp, i64, vp,
                                               i64, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                               ctypes.POINTER(i64)]),
@@ -249,14 +253,26 @@ class Plan:
 # Serving
 # ---------------------------------------------------------------------------
 class Server:
-    """Continuous-batching request loop (gol_serve_*)."""
+    """Continuous-batching request loop (gol_serve_*).
 
-    def __init__(self, hbm_budget_bytes: int = 64 << 30, chunk_generations: int = 64,
-                 device: int = 0, max_resident: int = 0, t_block: int = 0):
+    host_executor=True builds the scheduler over host memory instead of the
+    GPU (gol_debug_serve_create_host): for testing the scheduling policy; it
+    does not compute the Life rule."""
+
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, chunk_generations: int = 256,
+                 device: int = 0, max_resident: int = 0, t_block: int = 0,
+                 host_executor: bool = False, fail_at_chunk: int = 0):
         cfg = ServeConfig(hbm_budget_bytes, chunk_generations, device, max_resident, t_block)
         h = ctypes.c_void_p()
-        _check(lib().gol_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+        if host_executor:
+            _check(lib().gol_debug_serve_create_host(ctypes.byref(cfg), fail_at_chunk,
+                                                     ctypes.byref(h)))
+        else:
+            _check(lib().gol_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
+
+    def host_peak_bytes(self) -> int:
+        return int(lib().gol_debug_serve_host_peak_bytes(self._h))
 
     def submit(self, packed: np.ndarray, rows: int, cols: int, generations: int) -> int:
         a = np.ascontiguousarray(packed).view(np.uint64)
