@@ -25,8 +25,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes, 2.4 GHz peak engine clock.
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9          # 32-bit integer VALU ops/s
+# MI355X 32-bit VALU peak: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz
+# = 78.6 T ops/s, the published 157.3 TFLOP/s FP32 vector figure counted as
+# one op per FMA (integer and bitwise ops issue at the same lane rate).
+VALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
 HBM_PEAK_BYTES = 8.0e12
 # Algorithmic integer ops per cell-update of the bit-sliced step: per 32-cell
 # word and generation 2 funnel shifts + 2 (horizontal 3-sum) + 4 (vertical
@@ -70,11 +72,11 @@ def cpu_baseline(rows, cols, p, seed, budget_s=12.0):
                       f"{threads} OpenMP threads, byte-per-cell C oracle"}
 
 
-def measured_traffic(record: str, band_rows=None):
+def measured_traffic(record: str, cfg=None):
     """HBM bytes per launch from the committed counter record (rocprofv3
     FETCH_SIZE / WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when there is none for this kernel and tiling, or the kernel source has
-    changed since the counters were taken."""
+    when there is none for this kernel and launch configuration, or the kernel
+    source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(path):
@@ -83,19 +85,26 @@ def measured_traffic(record: str, band_rows=None):
     src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     if hashlib.sha256(src).hexdigest()[:16] != rec["source_sha256_16"]:
         return None
-    if band_rows is not None and rec.get("band_rows") not in (None, band_rows):
+    if cfg is not None and rec.get("config") != cfg:
         return None
     return rec["hbm_bytes_per_launch"]
 
 
-def roofline_alu(cells, T, avg_launch_s):
-    ops = OPS_PER_CELL_UPDATE * cells * T
-    pd = 6 if T >= 16 else 3
+def kernel_name(cfg):
+    """The tile-pass kernel a launch configuration runs."""
+    T, pd = cfg["t_block"], cfg["prefetch"]
+    if cfg["layout"] == 2:
+        return f"k_board_pass_half<{T}, {pd}>"
+    return f"k_board_pass<{T}, {pd}, true>"
+
+
+def roofline_alu(cells, cfg, avg_launch_s):
+    ops = OPS_PER_CELL_UPDATE * cells * cfg["t_block"]
     achieved = ops / avg_launch_s / 1e12
     peak = VALU_PEAK_OPS / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
             "frac": achieved / peak, "traffic": None,
-            "kernel": f"k_board_pass<{T}, {pd}>", "avg_launch_us": avg_launch_s * 1e6,
+            "kernel": kernel_name(cfg), "avg_launch_us": avg_launch_s * 1e6,
             "ops_per_launch": ops}
 
 
@@ -104,20 +113,20 @@ def roofline_hbm(cells, avg_launch_s):
     achieved = by / avg_launch_s / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
             "frac": achieved / (HBM_PEAK_BYTES / 1e9), "traffic": None,
-            "kernel": "k_board_pass<1, 3>", "avg_launch_us": avg_launch_s * 1e6,
+            "kernel": "k_board_pass<1, 3, true>", "avg_launch_us": avg_launch_s * 1e6,
             "bytes_per_launch": by}
 
 
-def time_packed(gol, torch, d_in, d_out, R, C, G, steps, warmup, T):
+def time_packed(gol, torch, d_in, d_out, R, C, G, steps, warmup, T, config=None):
     for _ in range(warmup):
-        gol.step_packed(d_in, R, C, G, d_out, t_block=T)
+        gol.step_packed(d_in, R, C, G, d_out, t_block=T, config=config)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(st)
     for _ in range(steps):
-        gol.step_packed(d_in, R, C, G, d_out, t_block=T)
+        gol.step_packed(d_in, R, C, G, d_out, t_block=T, config=config)
     e1.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -136,28 +145,35 @@ def single_board(args, R, C, G, p, label):
     del w
     d_out = torch.empty_like(d_in)
     torch.cuda.synchronize()
-    band = None
-    if args.t_block:
-        T = args.t_block
+    if args.config:
+        t, h, pd, lay = (int(v) for v in args.config.split(","))
+        cfg = {"t_block": t, "band_rows": h, "prefetch": pd, "layout": lay}
+    elif args.t_block:
+        cfg = {"t_block": args.t_block, "band_rows": 0, "prefetch": 0, "layout": 1}
     elif args.no_tune:
-        T = 8
+        cfg = {"t_block": 8, "band_rows": 0, "prefetch": 0, "layout": 1}
     else:
-        # one-off autotuning of (T, band height) for this size, before timing
-        T, band = gol.tune(R, C)
-        log(f"autotuned: T={T} band_rows={band}")
-    args.tuned = {"t_block": T, "band_rows": band}
-    log(f"timing {args.steps} steps after {args.warmup} warmup, T={T}")
-    wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, args.steps, args.warmup, T)
+        # one-off autotuning of the launch configuration for this size, before timing
+        cfg = gol.tune_config(R, C)
+        log(f"autotuned: {cfg}")
+    if not cfg["prefetch"]:
+        cfg["prefetch"] = {16: 12, 12: 9, 8: 9}.get(cfg["t_block"], 3)
+    args.tuned = cfg
+    T = cfg["t_block"]
+    log(f"timing {args.steps} steps after {args.warmup} warmup, {cfg}")
+    run_cfg = cfg if cfg["band_rows"] else None
+    wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, args.steps, args.warmup,
+                            0 if run_cfg else T, config=run_cfg)
     cells = R * C
     value = cells * G * args.steps / wall
     # average duration of one T-generation pass: device time per generation x T
-    # (a run of G = 1000 at T = 16 also holds one 8-generation pass)
+    # (a run of G = 1000 at T = 12 also holds one 4-generation pass)
     avg_launch = dev / (args.steps * G) * T
     res = {"value": value, "wall_s": wall, "dev_s": dev,
-           "roofline": roofline_alu(cells, T, avg_launch) if T > 1 else roofline_hbm(cells,
-                                                                                       avg_launch)}
-    rec = f"traffic_k_board_pass{T}_{R}x{C}.json"
-    res["roofline"]["traffic"] = measured_traffic(rec, band)
+           "roofline": roofline_alu(cells, cfg, avg_launch) if T > 1 else roofline_hbm(cells,
+                                                                                         avg_launch)}
+    rec = f"traffic_{res['roofline']['kernel'].split('<')[0]}_{R}x{C}.json"
+    res["roofline"]["traffic"] = measured_traffic(rec, cfg)
     extra = {}
     if args.compare_t1:
         wall1, dev1 = time_packed(gol, torch, d_in, d_out, R, C, G, max(1, args.steps // 2), 1, 1)
@@ -415,22 +431,19 @@ def sweep(args):
     d_out = torch.empty_like(d_in)
     nsimd = 4 * torch.cuda.get_device_properties(0).multi_processor_count
     D = 2 * ((C + 63) // 64)
-    nstrips = (D + 61) // 62
-    for T in (4, 8, 16):
-        for pd in (3, 6):
-            os.environ["GOL_PREFETCH"] = str(pd)
-            for k in (1, 2, 3, 4, 6, 8, 12, 16):
-                bands = max(1, (k * nsimd) // nstrips)
-                h = -(-R // bands)
-                if h < 8:
+    for layout, lanes, Ts in ((1, 62, ((8, 6), (8, 9), (12, 9), (16, 9), (16, 12))),
+                              (2, 30, ((8, 9), (12, 9), (12, 12), (16, 9), (16, 12)))):
+        nstrips = (D + lanes - 1) // lanes
+        for T, pd in Ts:
+            for k in (1, 2, 3, 4, 6, 8, 12):
+                units = max(1, (k * nsimd) // nstrips)
+                h = -(-R // (units if layout == 1 else 2 * units))
+                if h < T:
                     continue
-                os.environ["GOL_BAND_ROWS"] = str(h)
-                wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, 3, 1, T)
-                print(json.dumps({"T": T, "pd": pd, "k": k, "band_rows": h,
-                                  "waves": nstrips * (-(-R // h)),
-                                  "cell_updates_per_s": R * C * G * 3 / dev}), flush=True)
-    os.environ.pop("GOL_PREFETCH", None)
-    os.environ.pop("GOL_BAND_ROWS", None)
+                cfg = {"t_block": T, "band_rows": h, "prefetch": pd, "layout": layout}
+                wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, 3, 1, 0, config=cfg)
+                print(json.dumps({**cfg, "k": k, "cell_updates_per_s": R * C * G * 3 / dev}),
+                      flush=True)
 
 
 def main():
@@ -450,6 +463,9 @@ def main():
     ap.add_argument("--compare-t1", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (T = 8, model band)")
+    ap.add_argument("--config", default="",
+                    help="explicit launch configuration t_block,band_rows,prefetch,layout "
+                         "(layout 1 = one band per wave, 2 = paired bands); skips the autotuner")
     ap.add_argument("--sweep", action="store_true",
                     help="time T in {2,4,8,16} x band heights for the single-board workload")
     args = ap.parse_args()
@@ -515,6 +531,9 @@ def main():
                    "seed": SEED, "t_block": getattr(args, "tuned", {}).get("t_block",
                                                                           args.t_block or 8),
                    "band_rows": getattr(args, "tuned", {}).get("band_rows"),
+                   "prefetch": getattr(args, "tuned", {}).get("prefetch"),
+                   "layout": {1: "band", 2: "paired"}.get(getattr(args, "tuned", {})
+                                                          .get("layout")),
                    "parallelism": "single GPU"},
         "roofline": res["roofline"],
     }

@@ -73,7 +73,9 @@ int gol_step(const uint8_t* board, int64_t rows, int64_t cols, int64_t generatio
  * scratch (one board, two when d_out == d_in and the pass count is odd) from
  * the device's stream-ordered memory pool, or from the allocator installed
  * with gol_set_allocator.  `t_block` = generations per pass (the temporal
- * block): 0 picks the tuned default, else one of 1, 2, 4, 8, 16.
+ * block): 0 picks the tuned configuration for this size (see gol_tune), else
+ * one of 1, 2, 4, 8, 12, 16 with the default band height and layout.
+ * G mod t_block generations run first as shorter passes.
  */
 int gol_step_packed(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t generations,
                     uint64_t* d_out, void* stream);
@@ -81,16 +83,50 @@ int gol_step_packed_ex(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t
                        uint64_t* d_out, void* stream, int t_block);
 
 /*
- * Autotuner of the single-board path: times candidate (generations per pass,
- * band height) pairs for rows x cols boards on the current device, using two
- * scratch boards of that size from the stream-ordered pool (the pass's run
- * time does not depend on the cells), and remembers the fastest per
- * generation.  Later gol_step_packed / gol_step_packed_ex calls with
- * t_block = 0 on this device and size use it.  Synchronous on `stream`
- * (tens of milliseconds).  out_t_block / out_band_rows may be NULL.  If the
+ * Launch configuration of the single-board tile pass (Section 2's grid,
+ * split into tiles that each advance t_block generations per sweep of the
+ * board).  A field of 0 means automatic: when t_block and layout are both 0
+ * the autotuner's choice for this board size is used if gol_tune ran, and
+ * every field still 0 takes the built-in default.
+ *   t_block   generations per pass: 1, 2, 4, 8, 12 or 16.
+ *   band_rows rows per band (>= 1).
+ *   prefetch  rows requested ahead of use: GOL_LAYOUT_BAND 3 or 6 for
+ *             t_block <= 4, 6 or 9 for 8 and 12, 9 or 12 for 16;
+ *             GOL_LAYOUT_PAIRED 9 or 12.
+ *   layout    GOL_LAYOUT_BAND: one band of one strip per wave;
+ *             GOL_LAYOUT_PAIRED: two adjacent bands per wave that sweep
+ *             towards each other and trade the rows of their shared edge,
+ *             so only the outer edges of the pair recompute halo rows;
+ *             needs t_block 8, 12 or 16, cols % 32 == 0, a packed board
+ *             below 2 GiB and bands of at least t_block rows.
+ * Combinations outside these sets -> GOL_EINVAL with a message.
+ */
+#define GOL_LAYOUT_BAND 1
+#define GOL_LAYOUT_PAIRED 2
+typedef struct gol_pass_config {
+  int32_t t_block;
+  int32_t band_rows;
+  int32_t prefetch;
+  int32_t layout;
+} gol_pass_config;
+
+/* gol_step_packed with an explicit launch configuration (NULL = automatic). */
+int gol_step_packed_cfg(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t generations,
+                        uint64_t* d_out, void* stream, const gol_pass_config* config);
+
+/*
+ * Autotuner of the single-board path: times candidate launch configurations
+ * (both layouts, t_block 8, 12 and 16, several band heights) for rows x cols
+ * boards on the current device, using two scratch boards of that size from
+ * the stream-ordered pool (the pass's run time does not depend on the
+ * cells), and remembers the fastest per generation.  Later automatic calls
+ * on this device and size use it.  Synchronous on `stream` (tens to hundreds
+ * of milliseconds).  `out` (may be NULL) receives the choice.  If the
  * environment variable GOL_AUTOTUNE_CACHE names a file, choices are appended
  * to it and read back by later processes.
  */
+int gol_tune_cfg(int64_t rows, int64_t cols, void* stream, gol_pass_config* out);
+/* gol_tune_cfg reporting only t_block and band_rows (either may be NULL). */
 int gol_tune(int64_t rows, int64_t cols, void* stream, int* out_t_block, int* out_band_rows);
 
 /* Device conversions between the byte and packed layouts (asynchronous). */

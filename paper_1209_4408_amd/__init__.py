@@ -40,6 +40,11 @@ class Board(ctypes.Structure):
                 ("cols", ctypes.c_int64), ("generations", ctypes.c_int64)]
 
 
+class PassConfig(ctypes.Structure):
+    _fields_ = [("t_block", ctypes.c_int32), ("band_rows", ctypes.c_int32),
+                ("prefetch", ctypes.c_int32), ("layout", ctypes.c_int32)]
+
+
 class ServeConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("chunk_generations", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("max_resident", ctypes.c_int32),
@@ -82,6 +87,9 @@ def lib():
             "gol_step_packed": (c_int, [vp, i64, i64, i64, vp, vp]),
             "gol_step_packed_ex": (c_int, [vp, i64, i64, i64, vp, vp, c_int]),
             "gol_tune": (c_int, [i64, i64, vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
+            "gol_step_packed_cfg": (c_int, [vp, i64, i64, i64, vp, vp,
+                                            ctypes.POINTER(PassConfig)]),
+            "gol_tune_cfg": (c_int, [i64, i64, vp, ctypes.POINTER(PassConfig)]),
             "gol_pack": (c_int, [vp, i64, i64, vp, vp]),
             "gol_unpack": (c_int, [vp, i64, i64, vp, vp]),
             "gol_batch_run": (c_int, [vp, i64, vp]),
@@ -161,13 +169,25 @@ def empty_packed(rows: int, cols: int, device="cuda"):
     return torch.empty((rows, words_per_row(cols)), dtype=torch.int64, device=device)
 
 
+LAYOUT_BAND = 1
+LAYOUT_PAIRED = 2
+
+
 def step_packed(d_in, rows: int, cols: int, generations: int, d_out=None, stream=None,
-                t_block: int = 0):
-    """Packed device board -> packed device board (asynchronous on `stream`)."""
+                t_block: int = 0, config: dict | None = None):
+    """Packed device board -> packed device board (asynchronous on `stream`).
+
+    config: gol_pass_config fields as a dict (t_block, band_rows, prefetch,
+    layout; missing or 0 = automatic); when given, t_block is ignored."""
     if d_out is None:
         d_out = empty_packed(rows, cols, d_in.device)
-    _check(lib().gol_step_packed_ex(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
-                                    _stream_handle(stream), int(t_block)))
+    if config is not None:
+        c = PassConfig(**{k: int(v) for k, v in config.items()})
+        _check(lib().gol_step_packed_cfg(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
+                                         _stream_handle(stream), ctypes.byref(c)))
+    else:
+        _check(lib().gol_step_packed_ex(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
+                                        _stream_handle(stream), int(t_block)))
     return d_out
 
 
@@ -176,6 +196,14 @@ def tune(rows: int, cols: int, stream=None) -> tuple[int, int]:
     t, h = ctypes.c_int(), ctypes.c_int()
     _check(lib().gol_tune(rows, cols, _stream_handle(stream), ctypes.byref(t), ctypes.byref(h)))
     return t.value, h.value
+
+
+def tune_config(rows: int, cols: int, stream=None) -> dict:
+    """Autotune the single-board path for this size; returns the chosen
+    gol_pass_config as a dict."""
+    c = PassConfig()
+    _check(lib().gol_tune_cfg(rows, cols, _stream_handle(stream), ctypes.byref(c)))
+    return {f: getattr(c, f) for f, _ in PassConfig._fields_}
 
 
 def pack(d_bytes, rows: int, cols: int, d_out=None, stream=None):

@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdarg>
 #include <cstdio>
@@ -24,6 +25,8 @@ namespace gol {
 // Launchers defined in gol_kernels.hip.
 hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
                              int32_t D, const GridGeom& g, int pd, hipStream_t st);
+hipError_t launch_board_pass_half(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
+                                  int32_t D, const GridGeom& g, int pd, hipStream_t st);
 hipError_t launch_batch_pass(int T, bool masked, const BoardDesc* boards, const Segment* segs,
                              const WaveItem* items, int nitems, int level, hipStream_t st);
 hipError_t launch_pack(const uint8_t* in, int64_t R, int64_t C, uint64_t* out, hipStream_t st);
@@ -191,20 +194,67 @@ int simd_count() {
 // ---------------------------------------------------------------------------
 // Single board
 // ---------------------------------------------------------------------------
+// Band height of the paired layout when none is given: about two waves per
+// SIMD, as for the one-band layout.
+static int default_paired_rows(int64_t R, int64_t C, int nsimd) {
+  const int64_t D = 2 * ((C + 63) / 64);
+  const int64_t ns = (D + kHalfStripDwords - 1) / kHalfStripDwords;
+  const int64_t pairs = std::max<int64_t>(1, 2 * (int64_t)nsimd / ns);
+  return (int)std::max<int64_t>(1, (R + 2 * pairs - 1) / (2 * pairs));
+}
+
+int resolve_config(int64_t R, int64_t C, const PassConfig& want, PassConfig* out) {
+  PassConfig c = want;
+  if (c.T < 0 || c.band_rows < 0 || c.pd < 0 || c.layout < 0)
+    return set_error(GOL_EINVAL, "negative field in the pass configuration");
+  PassConfig tc;
+  if (want.T == 0 && want.layout == 0 && tuned_choice(R, C, &tc)) {
+    c.T = tc.T;
+    c.layout = tc.layout;
+    if (!c.band_rows) c.band_rows = tc.band_rows;
+    if (!c.pd) c.pd = tc.pd;
+  }
+  if (!c.T) c.T = default_T();
+  if (!c.layout) c.layout = kLayoutBand;
+  if (!c.pd) c.pd = default_prefetch(c.T);
+  if (!valid_board_T(c.T))
+    return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8, 12 or 16 (got %d)", c.T);
+  if (c.layout != kLayoutBand && c.layout != kLayoutPaired)
+    return set_error(GOL_EINVAL, "layout must be 0, 1 (band) or 2 (paired) (got %d)", c.layout);
+  if (!pass_config_compiled(c.layout, c.T, c.pd))
+    return set_error(GOL_EINVAL, "prefetch %d is not built for layout %d with t_block %d", c.pd,
+                     c.layout, c.T);
+  if (!c.band_rows)
+    c.band_rows = c.layout == kLayoutBand ? default_band_rows(R, C, c.T, simd_count())
+                                          : default_paired_rows(R, C, simd_count());
+  if (c.layout == kLayoutPaired) {
+    const char* why = nullptr;
+    if (!paired_ok(R, C, c.T, paired_geometry(R, C, c.band_rows, c.T, c.pd), &why))
+      return set_error(GOL_EINVAL, "%s", why);
+  }
+  *out = c;
+  return GOL_OK;
+}
+
+hipError_t launch_pass(const PassConfig& c, const uint32_t* src, uint32_t* dst, int64_t R,
+                       int64_t C, hipStream_t st) {
+  const int32_t D = (int32_t)(2 * ((C + 63) / 64));
+  if (c.layout == kLayoutPaired)
+    return launch_board_pass_half(c.T, src, dst, (int32_t)R, (int32_t)C, D,
+                                  paired_geometry(R, C, c.band_rows, c.T, c.pd), c.pd, st);
+  return launch_board_pass(c.T, src, dst, (int32_t)R, (int32_t)C, D,
+                           board_geometry(R, C, c.band_rows), c.pd, st);
+}
+
 int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t* d_out,
-                hipStream_t st, int T, int band_rows) {
+                hipStream_t st, const PassConfig& cfg) {
   int rc = check_board(R, C, G);
   if (rc) return rc;
   if (!d_in || !d_out) return set_error(GOL_EINVAL, "null board pointer");
-  if (T != 0 && !valid_T(T))
-    return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8 or 16 (got %d)", T);
-  // t_block 0: the autotuner's choice for this size if gol_tune ran, else the
-  // default T with the occupancy model's band height
-  TuneChoice tc{0, 0};
-  const bool tuned = tuned_choice(R, C, &tc);
-  if (T == 0) T = tuned ? tc.T : default_T();
-  if (band_rows <= 0 && tuned && tc.T == T) band_rows = tc.band_rows;
-  const int64_t W = (C + 63) / 64, D = 2 * W;
+  PassConfig c;
+  rc = resolve_config(R, C, cfg, &c);
+  if (rc) return rc;
+  const int64_t W = (C + 63) / 64;
   const size_t bytes = (size_t)(R * W * 8);
   if (ranges_partially_overlap(d_in, d_out, bytes))
     return set_error(GOL_EINVAL, "d_in and d_out partially overlap");
@@ -213,7 +263,7 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
     hipError_t e = launch_copy_clear_padding(d_in, R, C, d_out, st);
     return e == hipSuccess ? GOL_OK : hip_error(e, "copy kernel launch");
   }
-  const std::vector<int> passes = single_board_passes(G, T);
+  const std::vector<int> passes = single_board_passes(G, c.T);
   const int K = (int)passes.size();
   void* s1v = nullptr;
   rc = scratch_alloc(&s1v, bytes, st);
@@ -233,18 +283,17 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
   for (int j = 0; j < K && e == hipSuccess; ++j) {
     const uint32_t* src = (j == 0) ? src0 : w[(j - 1 + par) & 1];
     uint32_t* dst = w[(j + par) & 1];
-    const int Tj = passes[j];
-    int br = band_rows > 0 ? band_rows : default_band_rows(R, C, Tj, simd_count());
-    if (band_rows <= 0) {
-      // tuning override: GOL_BAND_ROWS=<rows>
-      const char* e = getenv("GOL_BAND_ROWS");
-      const int env_rows = e ? atoi(e) : 0;
-      if (env_rows > 0) br = env_rows;
+    if (passes[j] == c.T) {
+      e = launch_pass(c, src, dst, R, C, st);
+    } else {
+      // the G mod T remainder: shorter passes, one band per wave, defaults
+      PassConfig r;
+      r.T = passes[j];
+      r.layout = kLayoutBand;
+      r.pd = default_prefetch(r.T);
+      r.band_rows = default_band_rows(R, C, r.T, simd_count());
+      e = launch_pass(r, src, dst, R, C, st);
     }
-    const GridGeom g = board_geometry(R, C, br);
-    const char* pe = getenv("GOL_PREFETCH");  // tuning override: 3 or 6
-    const int pd = pe ? atoi(pe) : default_prefetch(Tj);
-    e = launch_board_pass(Tj, src, dst, (int32_t)R, (int32_t)C, (int32_t)D, g, pd, st);
   }
   scratch_free(s1v, st);
   if (e != hipSuccess) return hip_error(e, "tile pass launch");
@@ -295,7 +344,9 @@ int step_host(const uint8_t* board, int64_t R, int64_t C, int64_t G, uint8_t* ou
     e = hipMemcpyAsync(db, board, N, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_pack((const uint8_t*)db, R, C, (uint64_t*)pa, st);
     if (e == hipSuccess) {
-      rc = step_packed((const uint64_t*)pa, R, C, G, (uint64_t*)pb, st, T, 0);
+      PassConfig cfg;
+      cfg.T = T;
+      rc = step_packed((const uint64_t*)pa, R, C, G, (uint64_t*)pb, st, cfg);
       if (!rc) {
         e = launch_unpack((const uint64_t*)pb, R, C, (uint8_t*)db, st);
         if (e == hipSuccess) e = hipMemcpyAsync(out, db, N, hipMemcpyDeviceToHost, st);
@@ -496,7 +547,27 @@ int gol_step(const uint8_t* board, int64_t rows, int64_t cols, int64_t generatio
 int gol_step_packed_ex(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t generations,
                        uint64_t* d_out, void* stream, int t_block) {
   try {
-    return step_packed(d_in, rows, cols, generations, d_out, (hipStream_t)stream, t_block, 0);
+    PassConfig cfg;
+    cfg.T = t_block;
+    return step_packed(d_in, rows, cols, generations, d_out, (hipStream_t)stream, cfg);
+  } catch (const std::bad_alloc&) {
+    return set_error(GOL_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(GOL_EDEVICE, "unexpected exception");
+  }
+}
+
+int gol_step_packed_cfg(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t generations,
+                        uint64_t* d_out, void* stream, const gol_pass_config* config) {
+  try {
+    PassConfig cfg;
+    if (config) {
+      cfg.T = config->t_block;
+      cfg.band_rows = config->band_rows;
+      cfg.pd = config->prefetch;
+      cfg.layout = config->layout;
+    }
+    return step_packed(d_in, rows, cols, generations, d_out, (hipStream_t)stream, cfg);
   } catch (const std::bad_alloc&) {
     return set_error(GOL_ENOMEM, "host allocation failed");
   } catch (...) {

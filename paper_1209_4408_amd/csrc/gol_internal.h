@@ -18,6 +18,20 @@ constexpr int kMaxT = 32;
 constexpr int kWave = 64;
 // Useful columns of a strip that fills a whole wave: 64 lanes minus two halo lanes.
 constexpr int kStripDwords = kWave - 2;
+// Useful columns of a strip in one half of a wave (paired layout).
+constexpr int kHalfStripDwords = kWave / 2 - 2;
+
+// Layouts of the single-board tile pass.
+constexpr int kLayoutBand = 1;    // one band of one strip per wave
+constexpr int kLayoutPaired = 2;  // two adjacent bands per wave, sharing their edge
+
+// Prefetch distances (rows) compiled for each layout and pass length.
+constexpr bool pass_config_compiled(int layout, int T, int pd) {
+  return layout == kLayoutBand
+             ? (((T == 1 || T == 2 || T == 4) && (pd == 3 || pd == 6)) ||
+                ((T == 8 || T == 12) && (pd == 6 || pd == 9)) || (T == 16 && (pd == 9 || pd == 12)))
+             : layout == kLayoutPaired && (T == 8 || T == 12 || T == 16) && (pd == 9 || pd == 12);
+}
 
 // One board as seen by one launch of the pass kernel.  Pass j (0-based) of
 // the board reads  src0            if j == 0,

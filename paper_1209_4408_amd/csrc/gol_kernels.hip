@@ -342,7 +342,7 @@ __device__ __forceinline__ void tail(int i, int nsteps, Lane& L, Pipe<TM>& P, Ra
 template <int TM, bool MASKED, bool ALIGNED, int PD, bool BUFST>
 __device__ void run_tile(Lane& L, int H) {
   static_assert(TM >= 1 && TM <= kMaxT, "generations per pass");
-  static_assert(PD == 3 || PD == 6, "prefetch distance");
+  static_assert(PD % 3 == 0 && PD >= 3, "prefetch distance");
   Pipe<TM> P;
   Raw PF[PD];
   const int nsteps = H + 2 * TM;  // >= 3
@@ -374,7 +374,7 @@ struct PassArgs {
   int32_t R, C, D;
 };
 
-template <int TM, int PD>
+template <int TM, int PD, bool ALIGNED>
 __global__ __launch_bounds__(64) void k_board_pass(PassArgs a, GridGeom g) {
   const int nitems = g.nstrips * g.nbands;
   const int item = xcd_item(nitems);
@@ -389,10 +389,250 @@ __global__ __launch_bounds__(64) void k_board_pass(PassArgs a, GridGeom g) {
   Lane L;
   lane_setup(L, a.src, a.dst, a.R, a.C, a.D, ds - 1 + lane, lane, nl, rb, hb, TM, TM, lane < nl);
   if (!L.store) L.soff = kDroppedOffset;
-  if ((a.C & 31) == 0)
-    run_tile<TM, false, true, PD, true>(L, hb);
+  run_tile<TM, false, ALIGNED, PD, true>(L, hb);
+}
+
+// ---------------------------------------------------------------------------
+// Single board, paired bands in the two halves of one wave.
+//
+// A band swept on its own recomputes a cone of T rows beyond each of its
+// edges.  Here lanes 0-31 sweep band 2p downwards and lanes 32-63 sweep band
+// 2p + 1 upwards, over the same strip of at most 30 dwords (each half has its
+// own two halo lanes; the DPP shifts that cross lane 31 / 32 only touch halo
+// lanes), so both halves reach the edge between the bands at the end of
+// their sweeps.  There, instead of computing the other band's rows, the
+// halves trade them: stage s of one half needs generation s of the first
+// row beyond the edge, which is the other half's own edge row as its stage
+// s - 1 emitted it one step earlier.  Both halves run one instruction
+// stream, so the last T steps of the sweep (the epilogue) pass one row each
+// way with v_permlane32_swap, and stage e stops after epilogue step e; only
+// the outer edges of the pair keep a cone.  (The rule is symmetric under
+// reflection, so the upward sweep is the same pipeline over the rows in
+// reverse order.)
+//
+// Every band has the same height H, with H - T a multiple of the prefetch
+// distance, so the sweep reaches its epilogue at a step whose slot and
+// prefetch phases are known at compile time.  Pair p covers rows 2 p H ..
+// 2 p H + 2 H - 1 (mod R); when the pairs together cover more than R rows the
+// last pair overlaps the first, and both write the same (correct) next state
+// into the shared rows.  Rows go through buffer loads and stores at per-lane
+// byte offsets into the board (boards below 2 GiB); each half's row index is
+// a scalar that wraps around the torus.
+// ---------------------------------------------------------------------------
+// One stage at a step of slot phase PH (see stages): receive x, emit the
+// next generation of the row before it.
+template <int TM, int PH, int S>
+__device__ __forceinline__ uint32_t one_stage(uint32_t x, Pipe<TM>& P) {
+  constexpr int slot = ((PH - S) % 3 + 3) % 3;
+  constexpr int sa = (slot + 1) % 3;
+  constexpr int sc = (slot + 2) % 3;
+  const uint32_t xp = from_prev_lane(x);
+  const uint32_t xn = from_next_lane(x);
+  const uint32_t xl = __builtin_amdgcn_alignbit(x, xp, 31);
+  const uint32_t xr = __builtin_amdgcn_alignbit(xn, x, 1);
+  P.lo[S][slot] = xor3(xl, x, xr);
+  P.hi[S][slot] = maj3(xl, x, xr);
+  P.xs[S][slot] = x;
+  return life_rule(P.lo[S][sa], P.lo[S][sc], P.lo[S][slot], P.hi[S][sa], P.hi[S][sc],
+                   P.hi[S][slot], P.xs[S][sc]);
+}
+
+struct HalfLane {
+  int32_t R, D;
+  uint32_t in_off, in_step;    // byte offset of the lane's input dword, change per row
+  uint32_t out_off, out_step;  // same for the output (step 0 for lanes that never store)
+  uint32_t smask;
+  int32_t in_a, in_b;          // current input row of each half (uniform)
+  int32_t out_a, out_b;
+  uint32_t wrap;               // R * D * 4
+  bool upper;                  // lane in the upper half (band 2p + 1)
+};
+
+constexpr uint32_t kHalfDropped = 0xFFFFFF00u;
+
+// Next row of each half.  WRAP: some row of this wave's sweep lies across
+// the torus seam (only waves next to row 0 take that path).
+template <bool WRAP>
+__device__ __forceinline__ void half_advance_in(HalfLane& L) {
+  L.in_off += L.in_step;
+  if constexpr (WRAP) {
+    L.in_a += 1;
+    if (L.in_a == L.R) {  // uniform
+      L.in_a = 0;
+      if (!L.upper) L.in_off -= L.wrap;
+    }
+    L.in_b -= 1;
+    if (L.in_b < 0) {  // uniform
+      L.in_b += L.R;
+      if (L.upper) L.in_off += L.wrap;
+    }
+  }
+}
+
+template <bool WRAP>
+__device__ __forceinline__ void half_advance_out(HalfLane& L) {
+  L.out_off += L.out_step;
+  if constexpr (WRAP) {
+    L.out_a += 1;
+    if (L.out_a == L.R) {
+      L.out_a = 0;
+      if (!L.upper && L.out_step) L.out_off -= L.wrap;
+    }
+    L.out_b -= 1;
+    if (L.out_b < 0) {
+      L.out_b += L.R;
+      if (L.upper && L.out_step) L.out_off += L.wrap;
+    }
+  }
+}
+
+template <int TM, int PD, bool WRAP, int P3, int PP, bool PRO, int K>
+__device__ __forceinline__ void hstep(HalfLane& L, Pipe<TM>& P, uint32_t (&PF)[PD],
+                                      __amdgpu_buffer_rsrc_t src, __amdgpu_buffer_rsrc_t dst) {
+  uint32_t x = PF[PP];
+  PF[PP] = __builtin_amdgcn_raw_buffer_load_b32(src, L.in_off, 0, 0);
+  half_advance_in<WRAP>(L);
+  __builtin_amdgcn_sched_barrier(GOL_PREFETCH_FENCE_MASK);
+  Lane unused;  // read only by masked pipelines
+  stages<TM, false, P3, 0, PRO, K>(x, P, unused);
+  if constexpr (!PRO) {
+    __builtin_amdgcn_raw_buffer_store_b32(x & L.smask, dst, L.out_off, 0, 0);
+    half_advance_out<WRAP>(L);
+  }
+}
+
+template <int TM, int PD, bool WRAP, int K>
+__device__ __forceinline__ void hprologue(HalfLane& L, Pipe<TM>& P, uint32_t (&PF)[PD],
+                                          __amdgpu_buffer_rsrc_t src, __amdgpu_buffer_rsrc_t dst) {
+  if constexpr (K < 2 * TM) {
+    hstep<TM, PD, WRAP, K % 3, K % PD, true, K>(L, P, PF, src, dst);
+    hprologue<TM, PD, WRAP, K + 1>(L, P, PF, src, dst);
+  }
+}
+
+template <int TM, int PD, bool WRAP, int U>
+__device__ __forceinline__ void hbody(HalfLane& L, Pipe<TM>& P, uint32_t (&PF)[PD],
+                                      __amdgpu_buffer_rsrc_t src, __amdgpu_buffer_rsrc_t dst) {
+  if constexpr (U < PD) {
+    constexpr int k = 2 * TM + U;
+    hstep<TM, PD, WRAP, k % 3, k % PD, false, 0>(L, P, PF, src, dst);
+    hbody<TM, PD, WRAP, U + 1>(L, P, PF, src, dst);
+  }
+}
+
+template <int TM, int PD, bool WRAP, int U>
+__device__ __forceinline__ void htail(int i, int n, HalfLane& L, Pipe<TM>& P, uint32_t (&PF)[PD],
+                                      __amdgpu_buffer_rsrc_t src, __amdgpu_buffer_rsrc_t dst) {
+  if constexpr (U < PD - 1) {
+    if (i + U < n) {
+      constexpr int k = 2 * TM + U;
+      hstep<TM, PD, WRAP, k % 3, k % PD, false, 0>(L, P, PF, src, dst);
+      htail<TM, PD, WRAP, U + 1>(i, n, L, P, PF, src, dst);
+    }
+  }
+}
+
+// The other half's value of x (lane l receives lane l xor 32).
+__device__ __forceinline__ uint32_t swap_halves(uint32_t x, bool upper) {
+  const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return upper ? r[0] : r[1];
+}
+
+// Epilogue step at sweep step index K (mod 3), stages S .. TM - 1; stage
+// K - 2 TM (the one at the shared edge) hands its emitted row to `edge`.
+template <int TM, int K, int S>
+__device__ __forceinline__ void hepi_stages(uint32_t& x, Pipe<TM>& P, uint32_t& edge) {
+  if constexpr (S < TM) {
+    x = one_stage<TM, K % 3, S>(x, P);
+    if constexpr (S == K - 2 * TM) edge = x;
+    hepi_stages<TM, K, S + 1>(x, P, edge);
+  }
+}
+
+template <int TM, bool WRAP, int E>
+__device__ __forceinline__ void hepilogue(uint32_t xin, HalfLane& L, Pipe<TM>& P,
+                                          __amdgpu_buffer_rsrc_t dst) {
+  if constexpr (E < TM) {
+    uint32_t x = xin, edge = 0u;
+    // epilogue step E is sweep step H + TM + E, congruent to 2 TM + E mod 3
+    hepi_stages<TM, 2 * TM + E, E>(x, P, edge);
+    __builtin_amdgcn_raw_buffer_store_b32(x & L.smask, dst, L.out_off, 0, 0);
+    half_advance_out<WRAP>(L);
+    if constexpr (E + 1 < TM) {
+      // stage E emitted this half's edge row (generation E + 1); the other
+      // half's stage E + 1 receives it next step
+      hepilogue<TM, WRAP, E + 1>(swap_halves(edge, L.upper), L, P, dst);
+    }
+  }
+}
+
+// One wave's sweep: H + 2 TM steps, the last TM of them the epilogue.
+template <int TM, int PD, bool WRAP>
+__device__ void run_tile_half(HalfLane& L, int H, __amdgpu_buffer_rsrc_t rsrc,
+                              __amdgpu_buffer_rsrc_t rdst) {
+  Pipe<TM> P;
+  uint32_t PF[PD];
+#pragma unroll
+  for (int k = 0; k < PD; ++k) {
+    PF[k] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, L.in_off, 0, 0);
+    half_advance_in<WRAP>(L);
+  }
+  hprologue<TM, PD, WRAP, 0>(L, P, PF, rsrc, rdst);
+  // H - TM is a multiple of PD: whole loop bodies up to the epilogue
+  for (int i = 2 * TM; i < H + TM; i += PD) hbody<TM, PD, WRAP, 0>(L, P, PF, rsrc, rdst);
+  // the first row beyond the shared edge, loaded PD steps ago
+  hepilogue<TM, WRAP, 0>(PF[(2 * TM) % PD], L, P, rdst);
+}
+
+template <int TM, int PD>
+__global__ __launch_bounds__(64) void k_board_pass_half(PassArgs a, GridGeom g) {
+  const int npairs = g.nbands / 2;
+  const int nitems = g.nstrips * npairs;
+  const int item = xcd_item(nitems);
+  if (item >= nitems) return;  // whole wave
+  const int s = item % g.nstrips, pr = item / g.nstrips;
+  const int us = g.strip_q + (s < g.strip_r ? 1 : 0);
+  const int ds = s * g.strip_q + min(s, g.strip_r);
+  const int lane = (int)threadIdx.x;
+  const bool upper = lane >= 32;
+  const int l = lane & 31;
+  const int nl = us + 2;
+  const int R = a.R, D = a.D;
+  // half A: rows [a0, a0 + H) downwards; half B: rows [a0 + H, b1] upwards
+  const int H = g.band_q;
+  const int a0 = 2 * pr * H;
+  const int b1 = a0 + 2 * H - 1;  // may pass R: wraps
+  auto wrapr = [&](int r) { r %= R; return r < 0 ? r + R : r; };
+  HalfLane L;
+  L.R = R;
+  L.D = D;
+  L.upper = upper;
+  L.wrap = (uint32_t)R * (uint32_t)D * 4u;
+  L.in_a = wrapr(a0 - TM);
+  L.in_b = wrapr(b1 + TM);
+  L.out_a = wrapr(a0);
+  L.out_b = wrapr(b1);
+  const int p = ds - 1 + l;                     // logical dword of the lane
+  const int nd = a.C >> 5;                      // dwords holding cells (C % 32 == 0)
+  const int pc = ((p % nd) + nd) % nd;          // the dword its columns wrap to
+  const int rin = upper ? L.in_b : L.in_a;
+  const int rout = upper ? L.out_b : L.out_a;
+  L.in_off = ((uint32_t)rin * (uint32_t)D + (uint32_t)pc) * 4u;
+  L.in_step = upper ? (uint32_t)(-4 * D) : (uint32_t)(4 * D);
+  const bool store = l >= 1 && l <= nl - 2 && l < 31 && p >= 0 && p < D;
+  L.out_off = store ? ((uint32_t)rout * (uint32_t)D + (uint32_t)p) * 4u : kHalfDropped;
+  L.out_step = store ? L.in_step : 0u;
+  L.smask = p < nd ? 0xFFFFFFFFu : 0u;          // a padding dword stays 0
+  __amdgpu_buffer_rsrc_t rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.src, 0, (int)L.wrap, kBufferDword3);
+  __amdgpu_buffer_rsrc_t rdst = __builtin_amdgcn_make_buffer_rsrc(a.dst, 0, (int)L.wrap,
+                                                                   kBufferDword3);
+  // rows the sweep touches: A from a0 - TM to a0 + H + TM + PD, B the mirror
+  const bool wraps = a0 - TM < 0 || b1 + TM >= R || a0 + H + TM + PD >= R;
+  if (wraps)
+    run_tile_half<TM, PD, true>(L, H, rsrc, rdst);
   else
-    run_tile<TM, false, false, PD, true>(L, hb);
+    run_tile_half<TM, PD, false>(L, H, rsrc, rdst);
 }
 
 // ---------------------------------------------------------------------------
@@ -490,29 +730,60 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
 // ---------------------------------------------------------------------------
 // Host-side launchers (called by the C ABI in gol_capi.cpp).
 // ---------------------------------------------------------------------------
-template <int TM>
-static hipError_t launch_board_pass_t(const PassArgs& a, const GridGeom& g, int pd,
-                                      hipStream_t st) {
+template <int TM, int PD>
+static hipError_t launch_board_pass_t(const PassArgs& a, const GridGeom& g, hipStream_t st) {
   const int nitems = g.nstrips * g.nbands;
   const int grid = ((nitems + 7) / 8) * 8;
-  if (pd == 6)
-    hipLaunchKernelGGL((k_board_pass<TM, 6>), dim3(grid), dim3(64), 0, st, a, g);
+  if ((a.C & 31) == 0)
+    hipLaunchKernelGGL((k_board_pass<TM, PD, true>), dim3(grid), dim3(64), 0, st, a, g);
   else
-    hipLaunchKernelGGL((k_board_pass<TM, 3>), dim3(grid), dim3(64), 0, st, a, g);
+    hipLaunchKernelGGL((k_board_pass<TM, PD, false>), dim3(grid), dim3(64), 0, st, a, g);
   return hipGetLastError();
 }
 
+// One band per wave; (T, pd) must satisfy pass_config_compiled(kLayoutBand, ...).
 hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
                              int32_t D, const GridGeom& g, int pd, hipStream_t st) {
   PassArgs a{src, dst, R, C, D};
-  switch (T) {
-    case 1: return launch_board_pass_t<1>(a, g, pd, st);
-    case 2: return launch_board_pass_t<2>(a, g, pd, st);
-    case 4: return launch_board_pass_t<4>(a, g, pd, st);
-    case 8: return launch_board_pass_t<8>(a, g, pd, st);
-    case 16: return launch_board_pass_t<16>(a, g, pd, st);
-    default: return hipErrorInvalidValue;
+#define GOL_LAUNCH_BAND(TV, PDV) \
+  if (T == TV && pd == PDV) return launch_board_pass_t<TV, PDV>(a, g, st);
+  GOL_LAUNCH_BAND(1, 3)
+  GOL_LAUNCH_BAND(1, 6)
+  GOL_LAUNCH_BAND(2, 3)
+  GOL_LAUNCH_BAND(2, 6)
+  GOL_LAUNCH_BAND(4, 3)
+  GOL_LAUNCH_BAND(4, 6)
+  GOL_LAUNCH_BAND(8, 6)
+  GOL_LAUNCH_BAND(8, 9)
+  GOL_LAUNCH_BAND(12, 6)
+  GOL_LAUNCH_BAND(12, 9)
+  GOL_LAUNCH_BAND(16, 9)
+  GOL_LAUNCH_BAND(16, 12)
+#undef GOL_LAUNCH_BAND
+  return hipErrorInvalidValue;
+}
+
+// Two bands per wave; (T, pd) must satisfy pass_config_compiled(kLayoutPaired,
+// ...), g must come from paired_geometry with the same T and pd, C % 32 == 0
+// and the board must be smaller than 2 GiB.
+hipError_t launch_board_pass_half(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
+                                  int32_t D, const GridGeom& g, int pd, hipStream_t st) {
+  PassArgs a{src, dst, R, C, D};
+  const int nitems = g.nstrips * (g.nbands / 2);
+  const int grid = ((nitems + 7) / 8) * 8;
+#define GOL_LAUNCH_HALF(TV, PDV)                                                          \
+  if (T == TV && pd == PDV) {                                                             \
+    hipLaunchKernelGGL((k_board_pass_half<TV, PDV>), dim3(grid), dim3(64), 0, st, a, g);  \
+    return hipGetLastError();                                                             \
   }
+  GOL_LAUNCH_HALF(8, 9)
+  GOL_LAUNCH_HALF(8, 12)
+  GOL_LAUNCH_HALF(12, 9)
+  GOL_LAUNCH_HALF(12, 12)
+  GOL_LAUNCH_HALF(16, 9)
+  GOL_LAUNCH_HALF(16, 12)
+#undef GOL_LAUNCH_HALF
+  return hipErrorInvalidValue;
 }
 
 template <int TM, bool MASKED>

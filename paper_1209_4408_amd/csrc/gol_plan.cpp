@@ -2,6 +2,7 @@
 #include "gol_plan.h"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <map>
 #include <numeric>
@@ -9,6 +10,7 @@
 namespace gol {
 
 bool valid_T(int T) { return T == 1 || T == 2 || T == 4 || T == 8 || T == 16; }
+bool valid_board_T(int T) { return valid_T(T) || T == 12; }
 
 static int64_t dwords_per_row(int64_t cols) { return 2 * ((cols + 63) / 64); }
 
@@ -25,6 +27,38 @@ GridGeom board_geometry(int64_t rows, int64_t cols, int band_rows) {
   g.band_q = (int32_t)b.q;
   g.band_r = (int32_t)b.r;
   return g;
+}
+
+GridGeom paired_geometry(int64_t rows, int64_t cols, int band_rows, int T, int pd) {
+  const int64_t D = dwords_per_row(cols);
+  const int64_t ns = (D + kHalfStripDwords - 1) / kHalfStripDwords;
+  // band height: at least band_rows and T, with H - T a multiple of pd
+  int64_t H = std::max<int64_t>({1, (int64_t)band_rows, (int64_t)T});
+  if (pd > 0) H = T + ((H - T + pd - 1) / pd) * pd;
+  const int64_t npairs = std::max<int64_t>(1, (rows + 2 * H - 1) / (2 * H));
+  const Split s = split(D, ns);
+  GridGeom g;
+  g.nstrips = (int32_t)ns;
+  g.nbands = (int32_t)(2 * npairs);
+  g.strip_q = (int32_t)s.q;
+  g.strip_r = (int32_t)s.r;
+  g.band_q = (int32_t)std::min<int64_t>(H, INT32_MAX);
+  g.band_r = 0;
+  return g;
+}
+
+bool paired_ok(int64_t rows, int64_t cols, int T, const GridGeom& g, const char** why) {
+  const char* w = nullptr;
+  if (!(T == 8 || T == 12 || T == 16))
+    w = "the paired layout runs 8, 12 or 16 generations per pass";
+  else if (cols % 32 != 0)
+    w = "the paired layout needs a column count that is a multiple of 32";
+  else if (rows * dwords_per_row(cols) * 4 >= (int64_t(1) << 31))
+    w = "the paired layout needs a packed board below 2 GiB";
+  else if (g.band_q > 65535)
+    w = "the paired layout takes bands of at most 65535 rows";
+  if (why) *why = w;
+  return w == nullptr;
 }
 
 std::vector<int> single_board_passes(int64_t generations, int T) {
@@ -79,7 +113,7 @@ int default_band_rows(int64_t rows, int64_t cols, int T, int nsimd) {
   return (int)best_h;
 }
 
-int default_prefetch(int T) { return T >= 16 ? 6 : 3; }
+int default_prefetch(int T) { return T >= 16 ? 12 : T >= 8 ? 9 : 3; }
 
 namespace {
 struct ItemBuild {

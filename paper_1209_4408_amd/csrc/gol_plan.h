@@ -49,11 +49,21 @@ struct Split {
 };
 inline Split split(int64_t n, int64_t k) { return Split{n / k, n % k}; }
 
-// Grid of one large board for the single-board kernel.
+// Grid of one large board for the single-board kernel, one band per wave.
 GridGeom board_geometry(int64_t rows, int64_t cols, int band_rows);
 
+// Grid for the paired layout: strips of at most 30 dwords and pairs of bands
+// of one height H (band_q): the smallest H >= max(band_rows, T) with H - T a
+// multiple of pd; ceil(rows / 2H) pairs (nbands = 2 x pairs), pair p covering
+// rows 2 p H .. 2 p H + 2H - 1 mod rows (the last pair may overlap the first).
+GridGeom paired_geometry(int64_t rows, int64_t cols, int band_rows, int T, int pd);
+
+// Whether the paired layout runs this board with T generations per pass and
+// grid g; if not, *why says which condition fails.
+bool paired_ok(int64_t rows, int64_t cols, int T, const GridGeom& g, const char** why);
+
 // Pass lengths of a single board: powers of two for G mod T (small first),
-// then whole T passes.  Sum = G.
+// then whole T passes.  Sum = G.  Every length is a valid_board_T.
 std::vector<int> single_board_passes(int64_t generations, int T);
 
 // Builds the batch schedule.  Returns false with a message on invalid input.
@@ -68,6 +78,9 @@ int default_band_rows(int64_t rows, int64_t cols, int T, int nsimd);
 // Prefetch distance (rows) of the single-board kernel for T generations per pass.
 int default_prefetch(int T);
 
+// Generations per pass of the batched kernel.
 bool valid_T(int T);
+// Generations per pass of the single-board kernel.
+bool valid_board_T(int T);
 
 }  // namespace gol

@@ -28,15 +28,25 @@ bool ranges_partially_overlap(const void* a, const void* b, size_t bytes);
 int default_T();
 int simd_count();
 
-// Tuned (generations per pass, band height) for a board size.
-struct TuneChoice {
-  int T;
-  int band_rows;
+// Launch configuration of the single-board pass (gol_pass_config); 0 in a
+// field = automatic.
+struct PassConfig {
+  int T = 0;
+  int band_rows = 0;
+  int pd = 0;
+  int layout = 0;
 };
-bool tuned_choice(int64_t rows, int64_t cols, TuneChoice* out);
+// The autotuner's choice for a board size on the current device, if any.
+bool tuned_choice(int64_t rows, int64_t cols, PassConfig* out);
+// Fill the automatic fields (tuned choice, then defaults) and check the
+// result; GOL_EINVAL with a message if it cannot run this board.
+int resolve_config(int64_t R, int64_t C, const PassConfig& want, PassConfig* out);
+// One pass of T = c.T generations with a resolved configuration.
+hipError_t launch_pass(const PassConfig& c, const uint32_t* src, uint32_t* dst, int64_t R,
+                       int64_t C, hipStream_t st);
 
 int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t* d_out,
-                hipStream_t st, int T, int band_rows);
+                hipStream_t st, const PassConfig& cfg);
 
 // A batch schedule bound to device buffers.
 struct DevicePlan {

@@ -1,13 +1,16 @@
-// Autotuner of the single-board tile pass (gol_tune in include/gol.h).
+// Autotuner of the single-board tile pass (gol_tune / gol_tune_cfg in
+// include/gol.h).
 //
-// For a board size it times candidate (generations per pass T, band height)
-// pairs on scratch boards of that size and keeps the fastest per generation.
-// The pass's run time does not depend on the cells (bitwise network, no
-// data-dependent branches), so zeroed scratch boards time it faithfully.
-// Candidates: T in {4, 8, 16}; band counts that put the wave total just under
-// k waves per SIMD for k in {2, 3, 4, 6, 8, 12, 16}.  Results live in a
-// per-process table keyed by (device, rows, cols); when GOL_AUTOTUNE_CACHE
-// names a file, choices are also appended there and read back on first use.
+// For a board size it times candidate launch configurations on scratch
+// boards of that size and keeps the fastest per generation.  The pass's run
+// time does not depend on the cells (bitwise network, no data-dependent
+// branches), so zeroed scratch boards time it faithfully.  Candidates: both
+// layouts (one band per wave; two bands per wave sharing an edge, where the
+// board allows it), T in {8, 12, 16} with the prefetch distance that suits
+// it, and band heights that put about k waves on each SIMD for k in
+// {2, 3, 4, 6, 8}.  Results live in a per-process table keyed by (device,
+// rows, cols); when GOL_AUTOTUNE_CACHE names a file, choices are also
+// appended there and read back on first use.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -27,8 +30,6 @@
 
 namespace gol {
 
-hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
-                             int32_t D, const GridGeom& g, int pd, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 
 namespace {
@@ -40,9 +41,16 @@ struct Key {
   }
 };
 std::mutex g_mu;
-std::map<Key, TuneChoice> g_table;
+std::map<Key, PassConfig> g_table;
 bool g_loaded = false;
 
+bool usable(const PassConfig& c) {
+  return valid_board_T(c.T) && c.band_rows > 0 &&
+         (c.layout == kLayoutBand || c.layout == kLayoutPaired) &&
+         pass_config_compiled(c.layout, c.T, c.pd);
+}
+
+// Cache file lines: device rows cols t_block band_rows prefetch layout.
 void load_file_locked() {
   if (g_loaded) return;
   g_loaded = true;
@@ -50,24 +58,60 @@ void load_file_locked() {
   if (!path) return;
   FILE* f = fopen(path, "r");
   if (!f) return;
-  int dev, T, band;
+  int dev;
   long long rows, cols;
-  while (fscanf(f, "%d %lld %lld %d %d", &dev, &rows, &cols, &T, &band) == 5)
-    if (valid_T(T) && band > 0) g_table[Key{dev, rows, cols}] = TuneChoice{T, band};
+  PassConfig c;
+  while (fscanf(f, "%d %lld %lld %d %d %d %d", &dev, &rows, &cols, &c.T, &c.band_rows, &c.pd,
+                &c.layout) == 7)
+    if (usable(c)) g_table[Key{dev, rows, cols}] = c;
   fclose(f);
 }
 
-void save_locked(const Key& k, const TuneChoice& c) {
+void save_locked(const Key& k, const PassConfig& c) {
   const char* path = getenv("GOL_AUTOTUNE_CACHE");
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%d %lld %lld %d %d\n", k.dev, (long long)k.rows, (long long)k.cols, c.T, c.band_rows);
+  fprintf(f, "%d %lld %lld %d %d %d %d\n", k.dev, (long long)k.rows, (long long)k.cols, c.T,
+          c.band_rows, c.pd, c.layout);
   fclose(f);
+}
+
+// Configurations timed for an R x C board.
+std::vector<PassConfig> candidates(int64_t R, int64_t C, int nsimd) {
+  std::vector<PassConfig> out;
+  const int64_t D = 2 * ((C + 63) / 64);
+  for (int layout : {kLayoutBand, kLayoutPaired}) {
+    const int64_t lanes = layout == kLayoutBand ? kStripDwords : kHalfStripDwords;
+    const int64_t ns = (D + lanes - 1) / lanes;
+    for (int T : {8, 12, 16}) {
+      PassConfig c;
+      c.T = T;
+      c.layout = layout;
+      c.pd = layout == kLayoutPaired ? 9 : default_prefetch(T);
+      std::set<int64_t> heights;
+      for (int k : {2, 3, 4, 6, 8}) {
+        // waves: ns x bands (one band per wave) or ns x pairs (two per wave)
+        const int64_t units = std::max<int64_t>(1, (int64_t)k * nsimd / ns);
+        const int64_t per = layout == kLayoutBand ? units : 2 * units;
+        const int64_t h = std::max<int64_t>(1, (R + per - 1) / per);
+        if (h <= 65535) heights.insert(h);
+      }
+      if (layout == kLayoutBand) heights.insert(default_band_rows(R, C, T, nsimd));
+      for (int64_t h : heights) {
+        c.band_rows = (int)h;
+        if (layout == kLayoutPaired && !paired_ok(R, C, T, paired_geometry(R, C, c.band_rows, c.T, c.pd),
+                                                  nullptr))
+          continue;
+        out.push_back(c);
+      }
+    }
+  }
+  return out;
 }
 }  // namespace
 
-bool tuned_choice(int64_t rows, int64_t cols, TuneChoice* out) {
+bool tuned_choice(int64_t rows, int64_t cols, PassConfig* out) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return false;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -78,13 +122,13 @@ bool tuned_choice(int64_t rows, int64_t cols, TuneChoice* out) {
   return true;
 }
 
-int tune(int64_t R, int64_t C, hipStream_t st, TuneChoice* out) {
+int tune(int64_t R, int64_t C, hipStream_t st, PassConfig* out) {
   int rc = check_board(R, C, 0);
   if (rc) return rc;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_error(e, "hipGetDevice");
-  const int64_t W = (C + 63) / 64, D = 2 * W;
+  const int64_t W = (C + 63) / 64;
   const size_t bytes = (size_t)(R * W * 8);
   void *a = nullptr, *b = nullptr;
   rc = scratch_alloc(&a, bytes, st);
@@ -100,53 +144,41 @@ int tune(int64_t R, int64_t C, hipStream_t st, TuneChoice* out) {
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   const int nsimd = simd_count();
-  const int64_t ns = (D + kStripDwords - 1) / kStripDwords;
   double best = 1e300;
-  TuneChoice pick{default_T(), default_band_rows(R, C, default_T(), nsimd)};
-  for (int T : {4, 8, 16}) {
-    std::set<int64_t> heights;
-    for (int k : {2, 3, 4, 6, 8, 12, 16}) {
-      const int64_t bands = std::max<int64_t>(1, (int64_t)k * nsimd / ns);
-      const int64_t h = std::max<int64_t>(1, (R + bands - 1) / bands);
-      if (h <= 65535) heights.insert(h);
-    }
-    heights.insert(default_band_rows(R, C, T, nsimd));
-    const int pd = default_prefetch(T);
-    for (int64_t h : heights) {
-      if (e != hipSuccess) break;
-      const GridGeom g = board_geometry(R, C, (int)h);
-      // one warm-up pass, then enough passes for ~2 ms of device time
-      e = launch_board_pass(T, (const uint32_t*)a, (uint32_t*)b, (int32_t)R, (int32_t)C,
-                            (int32_t)D, g, pd, st);
-      if (e == hipSuccess) e = hipEventRecord(e0, st);
-      if (e == hipSuccess)
-        e = launch_board_pass(T, (const uint32_t*)b, (uint32_t*)a, (int32_t)R, (int32_t)C,
-                              (int32_t)D, g, pd, st);
-      if (e == hipSuccess) e = hipEventRecord(e1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) break;
-      int reps = (int)std::min(50.0, std::max(2.0, 2.0 / std::max(ms, 1e-3f)));
-      e = hipEventRecord(e0, st);
-      for (int i = 0; i < reps && e == hipSuccess; ++i)
-        e = launch_board_pass(T, (const uint32_t*)((i & 1) ? b : a), (uint32_t*)((i & 1) ? a : b),
-                              (int32_t)R, (int32_t)C, (int32_t)D, g, pd, st);
-      if (e == hipSuccess) e = hipEventRecord(e1, st);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) break;
-      const double per_gen = (double)ms / ((double)reps * T);
-      if (per_gen < best) {
-        best = per_gen;
-        pick = TuneChoice{T, (int)h};
-      }
+  PassConfig pick;
+  rc = resolve_config(R, C, PassConfig{}, &pick);  // the untuned default, if nothing wins
+  const uint32_t* pa = (const uint32_t*)a;
+  uint32_t* pb = (uint32_t*)b;
+  for (const PassConfig& c : candidates(R, C, nsimd)) {
+    if (e != hipSuccess || rc) break;
+    // one warm-up pass, then enough passes for about 2 ms of device time
+    e = launch_pass(c, pa, pb, R, C, st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch_pass(c, pb, (uint32_t*)pa, R, C, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) break;
+    const int reps = (int)std::min(50.0, std::max(2.0, 2.0 / std::max(ms, 1e-3f)));
+    e = hipEventRecord(e0, st);
+    for (int i = 0; i < reps && e == hipSuccess; ++i)
+      e = launch_pass(c, (i & 1) ? pb : pa, (i & 1) ? (uint32_t*)pa : pb, R, C, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) break;
+    const double per_gen = (double)ms / ((double)reps * c.T);
+    if (per_gen < best) {
+      best = per_gen;
+      pick = c;
     }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   scratch_free(b, st);
   scratch_free(a, st);
+  if (rc) return rc;
   if (e != hipSuccess) return hip_error(e, "gol_tune");
   {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -161,9 +193,8 @@ int tune(int64_t R, int64_t C, hipStream_t st, TuneChoice* out) {
 
 }  // namespace gol
 
-extern "C" int gol_tune(int64_t rows, int64_t cols, void* stream, int* out_t_block,
-                        int* out_band_rows) {
-  gol::TuneChoice c{0, 0};
+extern "C" int gol_tune_cfg(int64_t rows, int64_t cols, void* stream, gol_pass_config* out) {
+  gol::PassConfig c;
   int rc;
   try {
     rc = gol::tune(rows, cols, (hipStream_t)stream, &c);
@@ -171,7 +202,21 @@ extern "C" int gol_tune(int64_t rows, int64_t cols, void* stream, int* out_t_blo
     return gol::set_error(GOL_EDEVICE, "unexpected exception");
   }
   if (rc) return rc;
-  if (out_t_block) *out_t_block = c.T;
+  if (out) {
+    out->t_block = c.T;
+    out->band_rows = c.band_rows;
+    out->prefetch = c.pd;
+    out->layout = c.layout;
+  }
+  return GOL_OK;
+}
+
+extern "C" int gol_tune(int64_t rows, int64_t cols, void* stream, int* out_t_block,
+                        int* out_band_rows) {
+  gol_pass_config c{};
+  const int rc = gol_tune_cfg(rows, cols, stream, &c);
+  if (rc) return rc;
+  if (out_t_block) *out_t_block = c.t_block;
   if (out_band_rows) *out_band_rows = c.band_rows;
   return GOL_OK;
 }

@@ -140,3 +140,25 @@ def test_plan_rejects_bad_input():
         gol.plan_tables([4], [4], [-1])
     with pytest.raises(gol.GolError):
         gol.plan_tables([4], [4], [3], t_block=3)
+
+
+@pytest.mark.parametrize("cfg", [dict(t_block=5), dict(t_block=12, layout=2),   # cols % 32 != 0
+                                 dict(t_block=4, layout=2), dict(t_block=16, prefetch=3),
+                                 dict(t_block=8, prefetch=12), dict(layout=3),
+                                 dict(band_rows=-2), dict(t_block=16, layout=2, prefetch=6)])
+def test_pass_config_rejected_before_any_device_work(cfg):
+    """gol_step_packed_cfg checks the launch configuration on the host; the
+    device pointers are never touched (they are not even valid here)."""
+    c = gol.PassConfig(**{k: cfg.get(k, 0) for k in ("t_block", "band_rows", "prefetch",
+                                                     "layout")})
+    fake = ctypes.c_void_p(0x1000)
+    rc = gol.lib().gol_step_packed_cfg(fake, 64, 100, 5, fake, None, ctypes.byref(c))
+    assert rc == -1, (cfg, gol.lib().gol_last_error())
+
+
+def test_paired_layout_needs_a_board_below_2_gib():
+    c = gol.PassConfig(16, 0, 9, 2)
+    fake = ctypes.c_void_p(0x1000)
+    rc = gol.lib().gol_step_packed_cfg(fake, 131072, 131072, 5, fake, None, ctypes.byref(c))
+    assert rc == -1
+    assert b"2 GiB" in gol.lib().gol_last_error()

@@ -25,31 +25,37 @@ SEED = 1209
 
 
 def tuner_candidates(R, C):
-    """The (T, band height) pairs gol_tune times for an R x C board."""
+    """The launch configurations gol_tune times for an R x C board."""
     import torch
     nsimd = 4 * torch.cuda.get_device_properties(0).multi_processor_count
     D = 2 * ((C + 63) // 64)
-    ns = (D + 61) // 62
     out = []
-    for T in (4, 8, 16):
-        hs = set()
-        for k in (2, 3, 4, 6, 8, 12, 16):
-            bands = max(1, k * nsimd // ns)
-            hs.add(max(1, -(-R // bands)))
-        out += [(T, h) for h in sorted(hs)]
+    for layout, lanes in ((gol.LAYOUT_BAND, 62), (gol.LAYOUT_PAIRED, 30)):
+        ns = (D + lanes - 1) // lanes
+        for T in (8, 12, 16):
+            pd = 9 if layout == gol.LAYOUT_PAIRED else {8: 9, 12: 9, 16: 12}[T]
+            hs = set()
+            for k in (2, 3, 4, 6, 8):
+                units = max(1, k * nsimd // ns)
+                per = units if layout == gol.LAYOUT_BAND else 2 * units
+                hs.add(max(1, -(-R // per)))
+            for h in sorted(hs):
+                if layout == gol.LAYOUT_PAIRED and (C % 32 or R * D * 4 >= 1 << 31):
+                    continue
+                out.append(dict(t_block=T, band_rows=h, prefetch=pd, layout=layout))
     return out
 
 
-def all_candidates_agree(d_in, R, C, G, want):
-    """Every configuration the autotuner can pick gives the same board."""
-    for T, h in tuner_candidates(R, C):
-        os.environ["GOL_BAND_ROWS"] = str(h)
-        try:
-            say(f"  candidate T={T} band={h}")
-            got = from_dev(gol.step_packed(d_in, R, C, G, t_block=T))
-        finally:
-            os.environ.pop("GOL_BAND_ROWS", None)
-        assert np.array_equal(got, want), (T, h)
+def all_candidates_agree(d_in, R, C, G, want_dev):
+    """Every configuration the autotuner can pick gives the same board
+    (compared on the device)."""
+    import torch
+    d_out = torch.empty_like(d_in)
+    for cfg in tuner_candidates(R, C):
+        say(f"  candidate {cfg}")
+        gol.step_packed(d_in, R, C, G, d_out, config=cfg)
+        torch.cuda.synchronize()
+        assert torch.equal(d_out, want_dev), cfg
 
 
 def windows_ok(out_words, in_words, cols, G, spots, k):
@@ -67,13 +73,14 @@ def test_16384_board_1000_generations_windows():
     G = 1000
     w = seeded_inputs.board_packed(SEED, 0, R, C, 0.3)
     d_in = to_dev(w)
-    T, band = gol.tune(R, C)
-    say(f"16384^2 x 1000 on the GPU, tuned T={T} band={band}")
-    out = from_dev(gol.step_packed(d_in, R, C, G))
+    cfg = gol.tune_config(R, C)
+    say(f"16384^2 x 1000 on the GPU, tuned {cfg}")
+    d_out = gol.step_packed(d_in, R, C, G)
+    out = from_dev(d_out)
     assert oracle.padding_is_zero(out, C)
     spots = [(R - 6, C - 6), (R - 5, 7000), (9001, C - 4), (4321, 12345)]
     windows_ok(out, w, C, G, spots, 12)
-    all_candidates_agree(d_in, R, C, G, out)
+    all_candidates_agree(d_in, R, C, G, d_out)
 
 
 def test_16384_board_tiled_every_cell():
@@ -92,12 +99,14 @@ def c3_runs():
     G = 200
     w = seeded_inputs.board_packed(SEED, 0, R, C, 0.5)
     d_in = to_dev(w)
-    T, band = gol.tune(R, C)
-    say(f"65536^2 x 200, temporal-blocked, tuned T={T} band={band}")
-    tb = from_dev(gol.step_packed(d_in, R, C, G))
+    cfg = gol.tune_config(R, C)
+    say(f"65536^2 x 200, temporal-blocked, tuned {cfg}")
+    d_tb = gol.step_packed(d_in, R, C, G)
+    all_candidates_agree(d_in, R, C, G, d_tb)
+    tb = from_dev(d_tb)
+    del d_tb
     say("65536^2 x 200, one generation per launch")
     t1 = from_dev(gol.step_packed(d_in, R, C, G, t_block=1))
-    all_candidates_agree(d_in, R, C, G, tb)
     del d_in
     return w, tb, t1
 

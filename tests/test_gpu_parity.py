@@ -14,7 +14,7 @@ from gpu_util import expect_words, first_diff, from_dev, rand_bytes, say, to_dev
 
 pytestmark = pytest.mark.gpu
 
-T_BLOCKS = [1, 2, 4, 8, 16]
+T_BLOCKS = [1, 2, 4, 8, 12, 16]
 
 
 def run_packed(b, G, T=0, inplace=False):
@@ -147,8 +147,80 @@ def test_tiling_periodicity_on_gpu():
 
 
 def test_autotuned_choice_is_used_and_exact():
-    R, C, G = 700, 3000, 37
-    T, band = gol.tune(R, C)
-    assert T in (4, 8, 16) and 1 <= band <= R
-    b = rand_bytes(77, 1, R, C, 0.4)
-    check(b, G, 0)  # t_block 0 takes the tuned choice
+    for R, C, G in ((700, 3000, 37), (600, 2048, 45)):  # the second allows the paired layout
+        cfg = gol.tune_config(R, C)
+        assert cfg["t_block"] in (8, 12, 16) and 1 <= cfg["band_rows"] <= R
+        assert cfg["layout"] in (gol.LAYOUT_BAND, gol.LAYOUT_PAIRED)
+        b = rand_bytes(77, 1, R, C, 0.4)
+        check(b, G, 0)  # t_block 0 takes the tuned choice
+
+
+# ---------------------------------------------------------------------------
+# Explicit launch configurations (gol_step_packed_cfg)
+# ---------------------------------------------------------------------------
+PAIRED = [dict(t_block=8, prefetch=9), dict(t_block=8, prefetch=12), dict(t_block=12, prefetch=9),
+          dict(t_block=12, prefetch=12), dict(t_block=16, prefetch=9),
+          dict(t_block=16, prefetch=12)]
+
+# (rows, cols, generations, band_rows): pairs overlapping the first pair
+# (2 H x pairs > rows), boards whose cone wraps the torus, bands taller than
+# the board, C % 64 == 32 (a padding dword), one pair covering the whole
+# board, strips narrower than 30 dwords, several strips
+PAIRED_SHAPES = [(40, 64, 37, 20), (41, 32, 24, 10), (100, 96, 50, 25), (257, 4096, 30, 22),
+                 (300, 1984, 41, 37), (64, 2048, 33, 16), (33, 4064, 26, 16), (16, 320, 40, 8),
+                 (95, 1952, 29, 24), (130, 160, 17, 65), (7, 64, 30, 1), (1, 32, 20, 1),
+                 (23, 128, 19, 40)]
+
+
+def run_cfg(b, G, cfg, inplace=False):
+    R, C = b.shape
+    d_in = to_dev(oracle.pack(b))
+    d_out = d_in if inplace else gol.empty_packed(R, C)
+    gol.step_packed(d_in, R, C, G, d_out, config=cfg)
+    return from_dev(d_out)
+
+
+@pytest.mark.parametrize("cfg", PAIRED, ids=lambda c: f"T{c['t_block']}pd{c['prefetch']}")
+def test_paired_layout(cfg):
+    for R, C, G, h in PAIRED_SHAPES:
+        full = dict(cfg, layout=gol.LAYOUT_PAIRED, band_rows=h)
+        b = rand_bytes(4408, R * 7 + C, R, C, 0.4)
+        say(f"paired R={R} C={C} G={G} {full}")
+        got = run_cfg(b, G, full)
+        want = expect_words(b, G)
+        assert oracle.padding_is_zero(got, C)
+        assert np.array_equal(got, want), first_diff(got, want, C)
+
+
+def test_paired_layout_inplace_and_every_pass_count():
+    b = rand_bytes(12, 3, 96, 2048, 0.45)
+    for G in (12, 24, 36, 25, 47):  # 1, 2, 3 passes, with remainders
+        say("paired in place G", G)
+        got = run_cfg(b, G, dict(t_block=12, layout=gol.LAYOUT_PAIRED, band_rows=24), True)
+        assert np.array_equal(got, expect_words(b, G))
+
+
+@pytest.mark.parametrize("cfg", [dict(t_block=8, prefetch=6), dict(t_block=12, prefetch=6),
+                                 dict(t_block=12, prefetch=9), dict(t_block=16, prefetch=9),
+                                 dict(t_block=16, prefetch=12), dict(t_block=4, prefetch=6)],
+                         ids=lambda c: f"T{c['t_block']}pd{c['prefetch']}")
+def test_band_layout_configs(cfg):
+    for R, C, G, h in [(37, 100, 41, 9), (257, 4095, 30, 40), (70, 3969, 33, 7), (5, 5, 24, 2),
+                       (300, 2048, 50, 73)]:
+        full = dict(cfg, layout=gol.LAYOUT_BAND, band_rows=h)
+        b = rand_bytes(77, R + C, R, C, 0.4)
+        say(f"band R={R} C={C} G={G} {full}")
+        got = run_cfg(b, G, full)
+        assert np.array_equal(got, expect_words(b, G)), first_diff(got, expect_words(b, G), C)
+
+
+def test_config_errors():
+    R, C = 64, 100
+    d = gol.empty_packed(R, C)
+    for cfg in (dict(t_block=12, layout=gol.LAYOUT_PAIRED),          # C % 32 != 0
+                dict(t_block=4, layout=gol.LAYOUT_PAIRED),           # T not 8, 12, 16
+                dict(t_block=16, prefetch=3),                         # prefetch not built
+                dict(t_block=5), dict(layout=3), dict(band_rows=-1)):
+        with pytest.raises(gol.GolError) as e:
+            gol.step_packed(d, R, C, 5, config=cfg)
+        assert e.value.code == -1, cfg
