@@ -151,7 +151,7 @@ def single_board(args, R, C, G, p, label):
     elif args.t_block:
         cfg = {"t_block": args.t_block, "band_rows": 0, "prefetch": 0, "layout": 1}
     elif args.no_tune:
-        cfg = {"t_block": 8, "band_rows": 0, "prefetch": 0, "layout": 1}
+        cfg = {"t_block": 12, "band_rows": 0, "prefetch": 0, "layout": 1}
     else:
         # one-off autotuning of the launch configuration for this size, before timing
         cfg = gol.tune_config(R, C)
@@ -211,7 +211,8 @@ def batched(args):
     work = float(sum(s.rows * s.cols * s.generations for s in specs))
     log(f"generating {len(specs)} boards, {work:.3e} cell-updates")
     _, d_in, d_out, ins, outs = board_set_device(specs, SEED)
-    T = args.t_block or 8
+    T = args.t_block or 16
+    args.tuned = {"t_block": T}
     boards = [gol.BatchBoard(i, o, s.rows, s.cols, s.generations) for s, i, o in zip(specs, ins, outs)]
     st = torch.cuda.Stream()
     plan = gol.Plan(boards, t_block=T)
@@ -285,7 +286,7 @@ def host_api(args):
     w = oracle.pack(b)
     d_in = torch.from_numpy(w.view(np.int64)).cuda()
     d_out = torch.empty_like(d_in)
-    wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, 20, 3, args.t_block or 8)
+    wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, 20, 3, args.t_block)
     res = {"value": R * C * G / float(np.median(lat)), "wall_s": float(lat.sum()),
            "dev_s": dev, "roofline": None}
     extra = {"host_api_us": {"p50": float(np.median(lat) * 1e6),
@@ -326,7 +327,9 @@ def served(args):
     results = [None] * len(specs)
 
     def run_server():
-        srv = gol.Server(hbm_budget_bytes=64 << 30, chunk_generations=args.chunk)
+        srv = gol.Server(hbm_budget_bytes=64 << 30, chunk_generations=args.chunk,
+                         t_block=args.t_block)
+        args.tuned = {"t_block": args.t_block or 16}
         # warm the pools: one small request
         w = payloads[0]
         t = srv.submit(w, specs[0].rows, specs[0].cols, 1)
@@ -462,7 +465,7 @@ def main():
     ap.add_argument("--t-block", type=int, default=0)
     ap.add_argument("--compare-t1", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (T = 8, model band)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (T = 12, model band)")
     ap.add_argument("--config", default="",
                     help="explicit launch configuration t_block,band_rows,prefetch,layout "
                          "(layout 1 = one band per wave, 2 = paired bands); skips the autotuner")
@@ -529,7 +532,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "rows": R, "cols": C, "generations": G, "p": p,
                    "seed": SEED, "t_block": getattr(args, "tuned", {}).get("t_block",
-                                                                          args.t_block or 8),
+                                                                          args.t_block or 12),
                    "band_rows": getattr(args, "tuned", {}).get("band_rows"),
                    "prefetch": getattr(args, "tuned", {}).get("prefetch"),
                    "layout": {1: "band", 2: "paired"}.get(getattr(args, "tuned", {})

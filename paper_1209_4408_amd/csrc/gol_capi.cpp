@@ -168,10 +168,11 @@ bool ranges_partially_overlap(const void* a, const void* b, size_t bytes) {
   return x < y + bytes && y < x + bytes;
 }
 
-int default_T() { return 8; }
+int default_T() { return 12; }
+int default_batch_T() { return 16; }
 
 // Band height of batched schedules (tiles of many boards share a level).
-constexpr int kBatchBandRows = 64;
+constexpr int kBatchBandRows = 96;
 
 // SIMDs of the current device (4 per compute unit), cached per device.
 int simd_count() {
@@ -373,7 +374,7 @@ int step_host(const uint8_t* board, int64_t R, int64_t C, int64_t G, uint8_t* ou
 int plan_boards(const gol_board* boards, int64_t n, int T, int band_rows, DevicePlan& P) {
   if (n < 0 || (n > 0 && !boards)) return set_error(GOL_EINVAL, "bad board array");
   if (n > (int64_t)1 << 24) return set_error(GOL_EINVAL, "too many boards");
-  if (T == 0) T = default_T();
+  if (T == 0) T = default_batch_T();
   if (!valid_T(T)) return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8 or 16 (got %d)", T);
   std::vector<BoardReq> req((size_t)n);
   P.boards.assign(boards, boards + n);
@@ -734,7 +735,7 @@ int gol_debug_plan_tables(const int64_t* rows, const int64_t* cols, const int64_
     for (int64_t b = 0; b < n; ++b) req[b] = BoardReq{rows[b], cols[b], gens[b]};
     HostPlan hp;
     std::string err;
-    if (t_block == 0) t_block = default_T();
+    if (t_block == 0) t_block = default_batch_T();
     if (!build_plan(req, t_block, band_rows > 0 ? band_rows : 64, hp, err))
       return set_error(GOL_EINVAL, "%s", err.c_str());
     if (nsegs) *nsegs = (int64_t)hp.segs.size();

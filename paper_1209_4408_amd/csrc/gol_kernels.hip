@@ -39,7 +39,7 @@
 #endif
 // Prefetch distance (rows) of the batch kernel.
 #ifndef GOL_BATCH_PREFETCH
-#define GOL_BATCH_PREFETCH 3
+#define GOL_BATCH_PREFETCH 6
 #endif
 
 namespace gol {

@@ -25,7 +25,8 @@ void reap_deferred(bool wait);
 
 int check_board(int64_t rows, int64_t cols, int64_t gens);
 bool ranges_partially_overlap(const void* a, const void* b, size_t bytes);
-int default_T();
+int default_T();        // generations per pass of a single board without tuning
+int default_batch_T();  // of batched and served schedules
 int simd_count();
 
 // Launch configuration of the single-board pass (gol_pass_config); 0 in a

@@ -486,7 +486,7 @@ static int queue_chunk(Server& S, std::vector<uint64_t>& retire_now) {
   }
   if (act.empty()) return GOL_OK;
   const auto t_plan0 = std::chrono::steady_clock::now();
-  const int T = S.cfg.t_block ? S.cfg.t_block : default_T();
+  const int T = S.cfg.t_block ? S.cfg.t_block : default_batch_T();
   std::vector<BoardReq> req;
   req.reserve(act.size());
   for (Request* r : act) {

@@ -151,7 +151,7 @@ int tune(int64_t R, int64_t C, hipStream_t st, PassConfig* out) {
   uint32_t* pb = (uint32_t*)b;
   for (const PassConfig& c : candidates(R, C, nsimd)) {
     if (e != hipSuccess || rc) break;
-    // one warm-up pass, then enough passes for about 2 ms of device time
+    // one warm-up pass, then enough passes for about 6 ms of device time
     e = launch_pass(c, pa, pb, R, C, st);
     if (e == hipSuccess) e = hipEventRecord(e0, st);
     if (e == hipSuccess) e = launch_pass(c, pb, (uint32_t*)pa, R, C, st);
@@ -160,7 +160,7 @@ int tune(int64_t R, int64_t C, hipStream_t st, PassConfig* out) {
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e != hipSuccess) break;
-    const int reps = (int)std::min(50.0, std::max(2.0, 2.0 / std::max(ms, 1e-3f)));
+    const int reps = (int)std::min(200.0, std::max(3.0, 6.0 / std::max(ms, 1e-3f)));
     e = hipEventRecord(e0, st);
     for (int i = 0; i < reps && e == hipSuccess; ++i)
       e = launch_pass(c, (i & 1) ? pb : pa, (i & 1) ? (uint32_t*)pa : pb, R, C, st);
