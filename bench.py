@@ -29,6 +29,9 @@ sys.path.insert(0, ROOT)
 # = 78.6 T ops/s, the published 157.3 TFLOP/s FP32 vector figure counted as
 # one op per FMA (integer and bitwise ops issue at the same lane rate).
 VALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
+# Generations per pass of the batched and served schedules (the library's
+# default, passed explicitly so the reported configuration is the one run).
+BATCH_T = 12
 HBM_PEAK_BYTES = 8.0e12
 # Algorithmic integer ops per cell-update of the bit-sliced step: per 32-cell
 # word and generation 2 funnel shifts + 2 (horizontal 3-sum) + 4 (vertical
@@ -211,7 +214,7 @@ def batched(args):
     work = float(sum(s.rows * s.cols * s.generations for s in specs))
     log(f"generating {len(specs)} boards, {work:.3e} cell-updates")
     _, d_in, d_out, ins, outs = board_set_device(specs, SEED)
-    T = args.t_block or 16
+    T = args.t_block or BATCH_T
     args.tuned = {"t_block": T}
     boards = [gol.BatchBoard(i, o, s.rows, s.cols, s.generations) for s, i, o in zip(specs, ins, outs)]
     st = torch.cuda.Stream()
@@ -328,8 +331,8 @@ def served(args):
 
     def run_server():
         srv = gol.Server(hbm_budget_bytes=64 << 30, chunk_generations=args.chunk,
-                         t_block=args.t_block)
-        args.tuned = {"t_block": args.t_block or 16}
+                         t_block=args.t_block or BATCH_T)
+        args.tuned = {"t_block": args.t_block or BATCH_T}
         # warm the pools: one small request
         w = payloads[0]
         t = srv.submit(w, specs[0].rows, specs[0].cols, 1)
@@ -457,9 +460,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "copy"])
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=2700.0,
-                    help="Poisson arrival rate: 0.7 x batched capacity (4.2e13 cell-updates/s) / "
-                         "1.08e10 cell-updates per request")
-    ap.add_argument("--chunk", type=int, default=256)
+                    help="Poisson arrival rate; requests average 1.08e10 cell-updates, so "
+                         "2700/s offers 2.9e13 cell-updates/s, about 0.6 of the batched capacity")
+    ap.add_argument("--chunk", type=int, default=240)
     ap.add_argument("--plain-requests", type=int, default=4096)
     ap.add_argument("--boards", type=int, default=4096)
     ap.add_argument("--t-block", type=int, default=0)

@@ -287,7 +287,7 @@ class Server:
     GPU (gol_debug_serve_create_host): for testing the scheduling policy; it
     does not compute the Life rule."""
 
-    def __init__(self, hbm_budget_bytes: int = 64 << 30, chunk_generations: int = 256,
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, chunk_generations: int = 240,
                  device: int = 0, max_resident: int = 0, t_block: int = 0,
                  host_executor: bool = False, fail_at_chunk: int = 0):
         cfg = ServeConfig(hbm_budget_bytes, chunk_generations, device, max_resident, t_block)

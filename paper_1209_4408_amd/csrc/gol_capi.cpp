@@ -169,10 +169,10 @@ bool ranges_partially_overlap(const void* a, const void* b, size_t bytes) {
 }
 
 int default_T() { return 12; }
-int default_batch_T() { return 16; }
+int default_batch_T() { return 12; }
 
 // Band height of batched schedules (tiles of many boards share a level).
-constexpr int kBatchBandRows = 96;
+constexpr int kBatchBandRows = 64;
 
 // SIMDs of the current device (4 per compute unit), cached per device.
 int simd_count() {
@@ -375,7 +375,7 @@ int plan_boards(const gol_board* boards, int64_t n, int T, int band_rows, Device
   if (n < 0 || (n > 0 && !boards)) return set_error(GOL_EINVAL, "bad board array");
   if (n > (int64_t)1 << 24) return set_error(GOL_EINVAL, "too many boards");
   if (T == 0) T = default_batch_T();
-  if (!valid_T(T)) return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8 or 16 (got %d)", T);
+  if (!valid_T(T)) return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8, 12 or 16 (got %d)", T);
   std::vector<BoardReq> req((size_t)n);
   P.boards.assign(boards, boards + n);
   P.scratch_off.assign((size_t)n, 0);

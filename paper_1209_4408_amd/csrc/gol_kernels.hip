@@ -105,7 +105,7 @@ struct Lane {
   int32_t R, C, D;
   // gather of the lane's 32 logical columns: first n1 bits start at cell q
   // (dword ia, shift sh, continuing into dword ib), the rest come from the
-  // row start (dword 0); boards narrower than 32 cells take a bit loop.
+  // row start (dword 0); boards narrower than 32 cells repeat their row.
   int32_t ia, ib;
   uint32_t sh, n1, q;
   bool needB, needC, tiny;
@@ -199,12 +199,18 @@ __device__ __forceinline__ uint32_t window(const Raw& r, const Lane& L) {
     if (L.needC) w = (w & ((1u << L.n1) - 1u)) | (r.c << L.n1);
     return w;
   }
-  uint32_t w = 0u, pos = L.q;
-  for (int i = 0; i < 32; ++i) {
-    w |= ((r.a >> pos) & 1u) << i;
-    pos = (pos + 1u == (uint32_t)L.C) ? 0u : pos + 1u;
+  // C < 32: the row is dword 0 with zeros above cell C - 1.  Repeat it up the
+  // 64 bits of v by doubling (after k steps the first C 2^k bits are the row
+  // repeated), then read 32 bits from q <= 30.  A shift of 63 stands in for
+  // 64 or more: it only changes bit 63, which is never read.
+  uint64_t v = r.a;
+  uint32_t len = (uint32_t)L.C;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    v |= v << min(len, 63u);
+    len <<= 1;
   }
-  return w;
+  return (uint32_t)(v >> L.q);
 }
 
 __device__ __forceinline__ void advance_in(Lane& L) {
@@ -808,6 +814,8 @@ hipError_t launch_batch_pass(int T, bool masked, const BoardDesc* boards, const 
                           : launch_batch_pass_t<4, false>(boards, segs, items, nitems, level, st);
     case 8: return masked ? launch_batch_pass_t<8, true>(boards, segs, items, nitems, level, st)
                           : launch_batch_pass_t<8, false>(boards, segs, items, nitems, level, st);
+    case 12: return masked ? launch_batch_pass_t<12, true>(boards, segs, items, nitems, level, st)
+                           : launch_batch_pass_t<12, false>(boards, segs, items, nitems, level, st);
     case 16: return masked ? launch_batch_pass_t<16, true>(boards, segs, items, nitems, level, st)
                            : launch_batch_pass_t<16, false>(boards, segs, items, nitems, level, st);
     default: return hipErrorInvalidValue;

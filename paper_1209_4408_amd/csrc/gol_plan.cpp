@@ -9,8 +9,8 @@
 
 namespace gol {
 
-bool valid_T(int T) { return T == 1 || T == 2 || T == 4 || T == 8 || T == 16; }
-bool valid_board_T(int T) { return valid_T(T) || T == 12; }
+bool valid_T(int T) { return T == 1 || T == 2 || T == 4 || T == 8 || T == 12 || T == 16; }
+bool valid_board_T(int T) { return valid_T(T); }
 
 static int64_t dwords_per_row(int64_t cols) { return 2 * ((cols + 63) / 64); }
 
@@ -128,7 +128,7 @@ struct ItemBuild {
 bool build_plan(const std::vector<BoardReq>& boards, int T, int band_rows, HostPlan& plan,
                 std::string& err) {
   if (!valid_T(T)) {
-    err = "generations per pass must be 1, 2, 4, 8 or 16";
+    err = "generations per pass must be 1, 2, 4, 8, 12 or 16";
     return false;
   }
   if (band_rows < 1 || band_rows > 65535) {

@@ -78,7 +78,7 @@ int default_band_rows(int64_t rows, int64_t cols, int T, int nsimd);
 // Prefetch distance (rows) of the single-board kernel for T generations per pass.
 int default_prefetch(int T);
 
-// Generations per pass of the batched kernel.
+// Generations per pass of the batched kernel: 1, 2, 4, 8, 12, 16.
 bool valid_T(int T);
 // Generations per pass of the single-board kernel.
 bool valid_board_T(int T);

@@ -675,7 +675,7 @@ static int check_config(const gol_serve_config* cfg) {
   if (cfg->chunk_generations < 1) return set_error(GOL_EINVAL, "chunk_generations must be >= 1");
   if (cfg->hbm_budget_bytes == 0) return set_error(GOL_EINVAL, "hbm_budget_bytes must be > 0");
   if (cfg->t_block != 0 && !valid_T(cfg->t_block))
-    return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8 or 16");
+    return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8, 12 or 16");
   return GOL_OK;
 }
 

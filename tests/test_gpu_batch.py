@@ -21,7 +21,7 @@ def mixed_specs(seed, n):
     return out
 
 
-@pytest.mark.parametrize("T", [1, 4, 8, 16])
+@pytest.mark.parametrize("T", [1, 2, 4, 8, 12, 16])
 def test_batch_matches_oracle(T):
     specs = mixed_specs(T, 60)
     boards, ins, outs, want = [], [], [], []

@@ -67,7 +67,7 @@ def test_results_follow_the_buffers_across_chunks(chunk):
         assert st["cell_updates"] == sum(R * C * G for _, R, C, G in reqs)
 
 
-@pytest.mark.parametrize("T", [1, 4, 8, 16])
+@pytest.mark.parametrize("T", [1, 4, 8, 12, 16])
 def test_every_t_block_gives_the_requested_generations(T):
     reqs = [(board(k, 17 + k, 65 * k + 1), 17 + k, 65 * k + 1, g)
             for k, g in enumerate([1, 7, 8, 9, 31, 32, 33, 100])]
