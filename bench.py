@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
 # Generations per pass of the batched and served schedules (the library's
 # default, passed explicitly so the reported configuration is the one run).
-BATCH_T = 12
+BATCH_T = 16
 HBM_PEAK_BYTES = 8.0e12
 # Algorithmic integer ops per cell-update of the bit-sliced step: per 32-cell
 # word and generation 2 funnel shifts + 2 (horizontal 3-sum) + 4 (vertical
@@ -234,6 +234,12 @@ def batched(args):
         wall = time.perf_counter() - t0
     dev = e0.elapsed_time(e1) / 1e3
     value = work * args.steps / wall
+    plan.close()
+    levels = info["levels"]
+    res = {"value": value, "wall_s": wall, "dev_s": dev,
+           "roofline": roofline_alu_total(work, dev / args.steps, levels, T)}
+    if args.no_plain:
+        return res, {"plan": info}
     # plain: one launch sequence per board, sequential on one stream
     log("plain per-board loop")
     with torch.cuda.stream(st):
@@ -246,11 +252,6 @@ def batched(args):
         st.synchronize()
         wall_plain = time.perf_counter() - t0
     plain = work / wall_plain
-    plan.close()
-    # the batch kernel: algorithmic ops over the whole schedule / its device time
-    levels = info["levels"]
-    res = {"value": value, "wall_s": wall, "dev_s": dev,
-           "roofline": roofline_alu_total(work, dev / args.steps, levels, T)}
     extra = {"plain": {"value": plain, "unit": "cell-updates/s",
                        "what": "one gol_step_packed per board, sequential, same stream"},
              "speedup_vs_plain": value / plain, "plan": info}
@@ -468,6 +469,8 @@ def main():
     ap.add_argument("--t-block", type=int, default=0)
     ap.add_argument("--compare-t1", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched workload: skip the one-board-at-a-time comparison (profiling runs)")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (T = 12, model band)")
     ap.add_argument("--config", default="",
                     help="explicit launch configuration t_block,band_rows,prefetch,layout "

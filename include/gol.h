@@ -157,7 +157,7 @@ int gol_batch_run(const gol_board* boards, int64_t n, void* stream);
  * the first run and replayed afterwards).  The plan owns its scratch.
  */
 typedef struct gol_plan gol_plan;
-/* t_block: generations per pass, 0 = default (12), else 1, 2, 4, 8, 12 or 16. */
+/* t_block: generations per pass, 0 = default (16), else 1, 2, 4, 8, 12 or 16. */
 int gol_plan_create(const gol_board* boards, int64_t n, int t_block, gol_plan** out);
 int gol_plan_run(gol_plan* plan, void* stream);
 /* Describes the plan: waves per level 0, levels, total cell updates. */
@@ -176,7 +176,7 @@ typedef struct gol_serve_config {
   int32_t chunk_generations;   /* generations per tick (>= 1) */
   int32_t device;              /* HIP device ordinal */
   int32_t max_resident;        /* cap on resident boards (0 = no cap) */
-  int32_t t_block;             /* generations per pass: 0 = default (12), 1, 2, 4, 8, 12, 16 */
+  int32_t t_block;             /* generations per pass: 0 = default (16), 1, 2, 4, 8, 12, 16 */
 } gol_serve_config;
 
 typedef struct gol_server gol_server;

@@ -169,7 +169,7 @@ bool ranges_partially_overlap(const void* a, const void* b, size_t bytes) {
 }
 
 int default_T() { return 12; }
-int default_batch_T() { return 12; }
+int default_batch_T() { return 16; }
 
 // Band height of batched schedules (tiles of many boards share a level).
 constexpr int kBatchBandRows = 64;

@@ -205,6 +205,9 @@ __device__ __forceinline__ uint32_t window(const Raw& r, const Lane& L) {
   // 64 or more: it only changes bit 63, which is never read.
   uint64_t v = r.a;
   uint32_t len = (uint32_t)L.C;
+  // recompute the shift counts every row rather than hold five of them for
+  // the whole sweep (registers are allocated for the kernel's largest path)
+  asm volatile("" : "+v"(len));
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
     v |= v << min(len, 63u);
