@@ -100,21 +100,27 @@ __device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
 // Per-lane state of one tile sweep.
 // ---------------------------------------------------------------------------
 struct Lane {
-  const uint32_t* src;  // source board of this pass
-  uint32_t* dst;        // destination board of this pass
-  int32_t R, C, D;
-  // gather of the lane's 32 logical columns: first n1 bits start at cell q
-  // (dword ia, shift sh, continuing into dword ib), the rest come from the
-  // row start (dword 0); boards narrower than 32 cells repeat their row.
+  int32_t R, D;
+  // Gather of the lane's 32 logical columns from two words of the row:
+  // a = dword ia and b = dword ib.
+  //   C >= 64: the window starts at cell q = 32 ia + sh.  Where it stays
+  //     inside the row, b = dword ia + 1 supplies the bits past dword ia and
+  //     m1 = ~0; where it passes the row end after n1 < 32 cells, b = dword 0
+  //     (the row's start) and m1 keeps the n1 low bits:
+  //       window = m1 ? alignbit(b, a, sh) : b << n1   (bitwise select).
+  //   C < 64 (narrow): a, b = dwords 0 and 1 hold the whole row; it is
+  //     repeated up a 64-bit word and the window read from bit q, which sh
+  //     holds (and n1 holds C).
   int32_t ia, ib;
-  uint32_t sh, n1, q;
-  bool needB, needC, tiny;
+  uint32_t sh, n1, m1;
+  bool narrow;
   bool live;            // lane has a board in this launch
   // rows
   int32_t in_r;
   const uint32_t* in_row;
   int32_t out_r;
   uint32_t* out_row;
+  int64_t wrap;         // R * D: a row pointer that reaches row R moves back by this
   // store
   bool store;
   uint32_t soff;        // byte offset of the lane's dword in a row
@@ -127,36 +133,36 @@ __device__ __forceinline__ void lane_setup(Lane& L, const uint32_t* src, uint32_
                                            int32_t C, int32_t D, int32_t p, int32_t lane_in_seg,
                                            int32_t nlanes, int32_t r0, int32_t h, int32_t T,
                                            int32_t Tl, bool live) {
-  L.src = src;
-  L.dst = dst;
   L.R = R;
-  L.C = C;
   L.D = D;
   L.live = live;
   L.Tl = Tl;
   int64_t q64 = ((int64_t)p * 32) % (int64_t)C;
   if (q64 < 0) q64 += C;
   const uint32_t q = (uint32_t)q64;
-  L.q = q;
-  L.tiny = C < 32;
+  L.narrow = C < 64;
   const int32_t nd = (C + 31) >> 5;
-  if (!L.tiny) {
+  if (!L.narrow) {
+    // Only a right halo lane that follows a padding dword can need the
+    // dwords ia, ia + 1 and 0 at once; its cells never reach a stored word
+    // within T <= 32 generations, so it takes dword 0.
     L.ia = (int32_t)(q >> 5);
     L.sh = q & 31u;
-    L.n1 = (uint32_t)min((int64_t)32, (int64_t)C - (int64_t)q);
-    L.needB = L.sh != 0u && L.ia + 1 < nd;
-    L.ib = L.needB ? L.ia + 1 : L.ia;
-    L.needC = L.n1 < 32u;
+    const uint32_t n1 = (uint32_t)min((int64_t)32, (int64_t)C - (int64_t)q);
+    const bool past_end = n1 < 32u;
+    L.ib = past_end ? 0 : (L.sh != 0u && L.ia + 1 < nd ? L.ia + 1 : L.ia);
+    L.n1 = n1 & 31u;
+    L.m1 = past_end ? (1u << n1) - 1u : 0xFFFFFFFFu;
   } else {
     L.ia = 0;
-    L.ib = 0;
-    L.sh = 0;
-    L.n1 = 32;
-    L.needB = false;
-    L.needC = false;
+    L.ib = 1;  // D == 2
+    L.sh = q;
+    L.n1 = (uint32_t)C;
+    L.m1 = 0xFFFFFFFFu;
   }
   int64_t rin = ((int64_t)r0 - T) % (int64_t)R;
   if (rin < 0) rin += R;
+  L.wrap = (int64_t)R * D;
   L.in_r = (int32_t)rin;
   L.in_row = src + rin * (int64_t)D;
   L.out_r = r0;
@@ -169,51 +175,40 @@ __device__ __forceinline__ void lane_setup(Lane& L, const uint32_t* src, uint32_
 }
 
 struct Raw {
-  uint32_t a, b, c;
+  uint32_t a, b;
 };
 
 // Every lane loads every step from an address inside the board (idle lanes
-// and lanes whose gather needs fewer words read valid words they ignore), so
+// and lanes whose gather needs one word read a valid word they ignore), so
 // the loads carry no branch and the compiler can wait for each one alone.
 template <bool ALIGNED>
 __device__ __forceinline__ Raw load_raw(const Lane& L) {
   Raw r;
   r.a = L.in_row[L.ia];
-  if (!ALIGNED) {
-    r.b = L.in_row[L.ib];
-    r.c = L.in_row[0];
-  } else {
-    r.b = 0u;
-    r.c = 0u;
-  }
+  r.b = ALIGNED ? 0u : L.in_row[L.ib];
   return r;
 }
 
 template <bool ALIGNED>
 __device__ __forceinline__ uint32_t window(const Raw& r, const Lane& L) {
   if (ALIGNED) return r.a;
-  if (!L.tiny) {
-    // ib == ia when the window ends inside dword ia; the bits rotated in
-    // above it are then replaced by the wrapped part below.
-    uint32_t w = __builtin_amdgcn_alignbit(r.b, r.a, L.sh);
-    if (L.needC) w = (w & ((1u << L.n1) - 1u)) | (r.c << L.n1);
-    return w;
-  }
-  // C < 32: the row is dword 0 with zeros above cell C - 1.  Repeat it up the
-  // 64 bits of v by doubling (after k steps the first C 2^k bits are the row
-  // repeated), then read 32 bits from q <= 30.  A shift of 63 stands in for
-  // 64 or more: it only changes bit 63, which is never read.
-  uint64_t v = r.a;
-  uint32_t len = (uint32_t)L.C;
-  // recompute the shift counts every row rather than hold five of them for
-  // the whole sweep (registers are allocated for the kernel's largest path)
+  if (!L.narrow)
+    return __builtin_amdgcn_bitop3_b32(L.m1, __builtin_amdgcn_alignbit(r.b, r.a, L.sh),
+                                       r.b << L.n1, kSel);
+  // C < 64: the row, with its padding bits cleared (input padding is not
+  // trusted), repeated by doubling: after k steps the first C 2^k bits are
+  // the row over and over.  Five steps reach 32 cells past any q < C.
+  uint32_t len = L.n1;
+  // recompute the shift counts every row rather than hold them for the whole
+  // sweep (registers are allocated for the kernel's largest path)
   asm volatile("" : "+v"(len));
+  uint64_t v = ((uint64_t)r.b << 32 | r.a) & ((1ull << len) - 1ull);
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    v |= v << min(len, 63u);
+    v |= len < 64u ? v << len : 0ull;
     len <<= 1;
   }
-  return (uint32_t)(v >> L.q);
+  return (uint32_t)(v >> L.sh);
 }
 
 __device__ __forceinline__ void advance_in(Lane& L) {
@@ -221,7 +216,7 @@ __device__ __forceinline__ void advance_in(Lane& L) {
   L.in_row += L.D;
   if (L.in_r == L.R) {
     L.in_r = 0;
-    L.in_row = L.src;
+    L.in_row -= L.wrap;
   }
 }
 
@@ -230,7 +225,7 @@ __device__ __forceinline__ void advance_out(Lane& L) {
   L.out_row += L.D;
   if (L.out_r == L.R) {
     L.out_r = 0;
-    L.out_row = L.dst;
+    L.out_row -= L.wrap;
   }
 }
 

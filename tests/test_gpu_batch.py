@@ -53,6 +53,27 @@ def test_batch_run_one_shot_and_inplace():
         assert np.array_equal(from_dev(bb.d_out), want[i]), (i, specs[i])
 
 
+def test_batch_ignores_input_padding_bits():
+    """Bits at columns >= cols are not part of the board, whatever they hold."""
+    rng = np.random.default_rng(5)
+    boards, want = [], []
+    for i, C in enumerate([1, 3, 17, 31, 33, 40, 63, 65, 70, 100, 333, 2047]):
+        R = int(rng.integers(1, 90))
+        G = int(rng.integers(1, 40))
+        b = rand_bytes(8, i, R, C, 0.5)
+        w = oracle.pack(b)
+        if C % 64:
+            w[:, -1] |= ~np.uint64((1 << (C % 64)) - 1)  # every padding bit set
+        d = to_dev(w)
+        o = gol.empty_packed(R, C)
+        boards.append(gol.BatchBoard(d, o, R, C, G))
+        want.append((expect_words(b, G), (R, C, G)))
+    say("batch dirty padding", len(boards))
+    gol.batch_run(boards)
+    for bb, (wt, spec) in zip(boards, want):
+        assert np.array_equal(from_dev(bb.d_out), wt), spec
+
+
 def test_plan_graph_replays():
     """Replaying the captured plan from the same input gives the same result
     every time, with the program's own work in between."""

@@ -69,16 +69,29 @@ def test_inplace_odd_and_even_pass_counts():
         check(b, G, 8, inplace=True)
 
 
-def test_input_padding_bits_ignored():
-    R, C = 40, 100
-    b = rand_bytes(5, 5, R, C, 0.5)
-    w = oracle.pack(b)
-    w[:, -1] |= np.uint64(0xFFFFFFF000000000)  # set bits at columns >= 100
-    d_in = to_dev(w)
-    d_out = gol.empty_packed(R, C)
-    gol.step_packed(d_in, R, C, 9, d_out)
-    got = from_dev(d_out)
-    assert np.array_equal(got, expect_words(b, 9))
+def dirty_padding(w: np.ndarray, C: int, seed: int) -> np.ndarray:
+    """Packed words with random bits at every column >= C."""
+    w = w.copy()
+    if C % 64:
+        rng = np.random.default_rng(seed)
+        junk = rng.integers(0, 1 << 63, size=w.shape[0], dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+        w[:, -1] |= junk & ~np.uint64((1 << (C % 64)) - 1)
+    return w
+
+
+@pytest.mark.parametrize("C", [1, 5, 31, 33, 47, 63, 65, 70, 100, 127])
+def test_input_padding_bits_ignored(C):
+    R = 40
+    b = rand_bytes(5, C, R, C, 0.5)
+    w = dirty_padding(oracle.pack(b), C, C)
+    assert not np.array_equal(w, oracle.pack(b)) or C % 64 == 0
+    for T in (1, 8, 16):
+        say("dirty padding C", C, "T", T)
+        d_in = to_dev(w)
+        d_out = gol.empty_packed(R, C)
+        gol.step_packed(d_in, R, C, 9 + T, d_out, t_block=T)
+        got = from_dev(d_out)
+        assert np.array_equal(got, expect_words(b, 9 + T)), (C, T)
 
 
 def test_patterns_on_gpu():
