@@ -178,14 +178,22 @@ struct Raw {
   uint32_t a, b;
 };
 
+// Boards live in global memory.  Pointers read from the batch tables are
+// generic to the compiler, and a generic (flat) load may be an LDS access that
+// completes out of order, so each use of a flat load's result would wait for
+// every load in flight and defeat the prefetch ring; global-address-space
+// accesses complete in order and can be waited for one at a time.
+typedef const __attribute__((address_space(1))) uint32_t* GlobalIn;
+typedef __attribute__((address_space(1))) uint32_t* GlobalOut;
+
 // Every lane loads every step from an address inside the board (idle lanes
 // and lanes whose gather needs one word read a valid word they ignore), so
 // the loads carry no branch and the compiler can wait for each one alone.
 template <bool ALIGNED>
 __device__ __forceinline__ Raw load_raw(const Lane& L) {
   Raw r;
-  r.a = L.in_row[L.ia];
-  r.b = ALIGNED ? 0u : L.in_row[L.ib];
+  r.a = ((GlobalIn)L.in_row)[L.ia];
+  r.b = ALIGNED ? 0u : ((GlobalIn)L.in_row)[L.ib];
   return r;
 }
 
@@ -305,7 +313,7 @@ __device__ __forceinline__ void step(int i, int nsteps, Lane& L, Pipe<TM>& P, Ra
       __builtin_amdgcn_raw_buffer_store_b32(x & L.smask, rs, L.soff, 0, 0);
     } else {
       if (L.store && i - 2 * TM < L.hl)
-        *(uint32_t*)((char*)L.out_row + L.soff) = x & L.smask;
+        *(GlobalOut)((char*)L.out_row + L.soff) = x & L.smask;
     }
     advance_out(L);
   }
