@@ -9,14 +9,20 @@
  *     halo, lane), int32 r0 (first output row), uint16 h (output rows),
  *     uint8 lane0, uint8 nlanes;
  *   wave item (16 bytes): int32 seg_begin, int16 nseg, uint16 h (largest
- *     band), int32 maxK (levels the wave takes part in), int32 flags
+ *     band), int32 maxK (largest pass count of its boards), int32 flags
  *     (bit 0: every lane's board has cols % 32 == 0);
- *   level_items[L]: waves launched at level L (a prefix of the items).
+ *   levels[2 L], levels[2 L + 1]: level L launches the waves
+ *     [0, levels[2 L]) and [*late_begin, *late_begin + levels[2 L + 1]) —
+ *     a prefix of the early group (waves running levels 0 .. maxK - 1) and
+ *     of the late group (levels Kmax - maxK .. Kmax - 1, Kmax = the number
+ *     of levels);
+ *   starts[b]: the level of board b's first pass (n entries; boards with no
+ *     generations: 0).
  * rows / cols / gens: n entries each.  t_block: generations per pass (0 =
  * default).  band_rows: rows per tile band (0 = default).  Up to cap_* entries
- * are written to each non-NULL output; *nsegs, *nitems, *nlevels receive the
- * full counts.  Returns GOL_OK, GOL_EINVAL (bad sizes or t_block) or
- * GOL_ENOMEM.  Thread-safe; owns nothing after it returns.
+ * (cap_levels pairs) are written to each non-NULL output; *nsegs, *nitems,
+ * *nlevels receive the full counts.  Returns GOL_OK, GOL_EINVAL (bad sizes or
+ * t_block) or GOL_ENOMEM.  Thread-safe; owns nothing after it returns.
  */
 #ifndef GOL_DEBUG_H
 #define GOL_DEBUG_H
@@ -29,8 +35,9 @@ extern "C" {
 
 int gol_debug_plan_tables(const int64_t* rows, const int64_t* cols, const int64_t* gens, int64_t n,
                           int t_block, int band_rows, void* segs, int64_t cap_segs, void* items,
-                          int64_t cap_items, int32_t* level_items, int64_t cap_levels,
-                          int64_t* nsegs, int64_t* nitems, int64_t* nlevels);
+                          int64_t cap_items, int32_t* levels, int64_t cap_levels,
+                          int32_t* starts, int32_t* late_begin, int64_t* nsegs, int64_t* nitems,
+                          int64_t* nlevels);
 
 /*
  * A server whose "device" is host memory, for testing the serving scheduler

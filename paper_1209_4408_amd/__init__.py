@@ -111,7 +111,8 @@ def lib():
                                                     ctypes.POINTER(vp)]),
             "gol_debug_serve_host_peak_bytes": (i64, [vp]),
             "gol_debug_plan_tables": (c_int, [vp, vp, vp, i64, c_int, c_int, vp, i64, vp, i64, vp,
-                                              i64, ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                              i64, vp, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(i64), ctypes.POINTER(i64),
                                               ctypes.POINTER(i64)]),
         }
         for name, (res, args) in sig.items():
@@ -364,19 +365,28 @@ WAVEITEM_DTYPE = np.dtype([("seg_begin", "<i4"), ("nseg", "<i2"), ("h", "<u2"), 
 
 def plan_tables(rows: Iterable[int], cols: Iterable[int], generations: Iterable[int],
                 t_block: int = 8, band_rows: int = 64):
+    """The batch schedule the library would build for these boards (host only).
+
+    Returns (segs, items, levels, late_begin, starts): levels[L] = (early, late)
+    wave counts of level L, which launches items[:early] and
+    items[late_begin:late_begin + late]; starts[b] = level of board b's first
+    pass."""
     r = np.ascontiguousarray(list(rows), dtype=np.int64)
     c = np.ascontiguousarray(list(cols), dtype=np.int64)
     g = np.ascontiguousarray(list(generations), dtype=np.int64)
     ns, ni, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    lb = ctypes.c_int32()
     _check(lib().gol_debug_plan_tables(r.ctypes.data, c.ctypes.data, g.ctypes.data, len(r),
-                                       t_block, band_rows, None, 0, None, 0, None, 0,
-                                       ctypes.byref(ns), ctypes.byref(ni), ctypes.byref(nl)))
+                                       t_block, band_rows, None, 0, None, 0, None, 0, None,
+                                       ctypes.byref(lb), ctypes.byref(ns), ctypes.byref(ni),
+                                       ctypes.byref(nl)))
     segs = np.zeros(ns.value, dtype=SEGMENT_DTYPE)
     items = np.zeros(ni.value, dtype=WAVEITEM_DTYPE)
-    levels = np.zeros(nl.value, dtype=np.int32)
+    levels = np.zeros((nl.value, 2), dtype=np.int32)
+    starts = np.zeros(len(r), dtype=np.int32)
     _check(lib().gol_debug_plan_tables(r.ctypes.data, c.ctypes.data, g.ctypes.data, len(r),
                                        t_block, band_rows, segs.ctypes.data, len(segs),
                                        items.ctypes.data, len(items), levels.ctypes.data,
-                                       len(levels), ctypes.byref(ns), ctypes.byref(ni),
-                                       ctypes.byref(nl)))
-    return segs, items, levels
+                                       len(levels), starts.ctypes.data, ctypes.byref(lb),
+                                       ctypes.byref(ns), ctypes.byref(ni), ctypes.byref(nl)))
+    return segs, items, levels, int(lb.value), starts

@@ -28,7 +28,8 @@ hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t 
 hipError_t launch_board_pass_half(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
                                   int32_t D, const GridGeom& g, int pd, hipStream_t st);
 hipError_t launch_batch_pass(int T, bool masked, const BoardDesc* boards, const Segment* segs,
-                             const WaveItem* items, int nitems, int level, hipStream_t st);
+                             const WaveItem* items, int nearly, int nlate, int late_begin,
+                             int level, hipStream_t st);
 hipError_t launch_pack(const uint8_t* in, int64_t R, int64_t C, uint64_t* out, hipStream_t st);
 hipError_t launch_unpack(const uint64_t* in, int64_t R, int64_t C, uint8_t* out, hipStream_t st);
 hipError_t launch_copy_clear_padding(const uint64_t* in, int64_t R, int64_t C, uint64_t* out,
@@ -172,7 +173,7 @@ int default_T() { return 12; }
 int default_batch_T() { return 16; }
 
 // Band height of batched schedules (tiles of many boards share a level).
-constexpr int kBatchBandRows = 64;
+constexpr int kBatchBandRows = 96;
 
 // SIMDs of the current device (4 per compute unit), cached per device.
 int simd_count() {
@@ -418,7 +419,9 @@ void fill_board_descs(DevicePlan& P) {
     d.C = (int32_t)g.cols;
     d.D = (int32_t)(2 * W);
     d.K = P.hp.K[b];
-    d.Tfirst = P.hp.Tfirst[b];
+    d.Tshort = P.hp.Tshort[b];
+    d.start = P.hp.start[b];
+    d.jshort = P.hp.jshort[b];
     if (d.K == 0) {
       P.zero_gen.push_back((int)b);
       d.src0 = (const uint32_t*)g.d_in;
@@ -438,7 +441,35 @@ void fill_board_descs(DevicePlan& P) {
   }
 }
 
-hipError_t enqueue_plan(const DevicePlan& P, hipStream_t st) {
+hipError_t enqueue_levels(const HostPlan& hp, const BoardDesc* boards, const Segment* segs,
+                          const WaveItem* items, hipStream_t st, hipStream_t side,
+                          hipEvent_t fork, hipEvent_t join) {
+  const int Kmax = (int)hp.level_items.size();
+  const bool two = Kmax > 0 && hp.late_begin < (int32_t)hp.items.size();
+  hipError_t e = hipSuccess;
+  if (two) {
+    e = hipEventRecord(fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+  }
+  for (int L = 0; L < Kmax && e == hipSuccess; ++L) {
+    if (hp.level_early[L] > 0)
+      e = launch_batch_pass(hp.T, L == 0 && hp.early_masked, boards, segs, items,
+                            hp.level_early[L], 0, hp.late_begin, L, st);
+    if (e == hipSuccess && hp.level_late[L] > 0)
+      e = launch_batch_pass(hp.T, L == Kmax - 1 && hp.late_masked, boards, segs, items, 0,
+                            hp.level_late[L], hp.late_begin, L, two ? side : st);
+  }
+  if (two) {
+    // join even after a failed launch, so a capture on `st` can end
+    hipError_t e2 = hipEventRecord(join, side);
+    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(st, join, 0);
+    if (e == hipSuccess) e = e2;
+  }
+  return e;
+}
+
+hipError_t enqueue_plan(const DevicePlan& P, hipStream_t st, hipStream_t side, hipEvent_t fork,
+                        hipEvent_t join) {
   hipError_t e = hipSuccess;
   for (int b : P.zero_gen) {
     const gol_board& g = P.boards[b];
@@ -450,12 +481,7 @@ hipError_t enqueue_plan(const DevicePlan& P, hipStream_t st) {
     e = launch_copy_clear_padding(g.d_in, g.rows, g.cols, P.d_scratch + P.scratch_off[b], st);
     if (e != hipSuccess) return e;
   }
-  for (size_t L = 0; L < P.hp.level_items.size(); ++L) {
-    e = launch_batch_pass(P.hp.T, L == 0 && P.hp.level0_masked, P.d_boards, P.d_segs, P.d_items,
-                          P.hp.level_items[L], (int)L, st);
-    if (e != hipSuccess) return e;
-  }
-  return e;
+  return enqueue_levels(P.hp, P.d_boards, P.d_segs, P.d_items, st, side, fork, join);
 }
 
 // Uploads boards / segments / items into one device block at `dev`.
@@ -473,12 +499,34 @@ static void fill_meta_host(const DevicePlan& P, char* host, size_t ob, size_t os
   memcpy(host + oi, P.hp.items.data(), P.hp.items.size() * sizeof(WaveItem));
 }
 
+// A pooled library stream and two events for enqueue_levels' second stream.
+// The events may be destroyed once the waits on them are queued.
+struct SideStream {
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  int open() {
+    int rc = acquire_stream(&st);
+    if (rc) return rc;
+    hipError_t e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    return e == hipSuccess ? GOL_OK : hip_error(e, "hipEventCreate");
+  }
+  ~SideStream() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (st) release_stream(st);
+  }
+};
+
 int batch_run(const gol_board* boards, int64_t n, hipStream_t st, int T) {
   reap_deferred(false);
   DevicePlan P;
   int rc = plan_boards(boards, n, T, 0, P);
   if (rc) return rc;
   if (n == 0) return GOL_OK;
+  SideStream side;
+  rc = side.open();
+  if (rc) return rc;
   void* scratch = nullptr;
   void* meta = nullptr;
   if (P.scratch_words) {
@@ -506,7 +554,7 @@ int batch_run(const gol_board* boards, int64_t n, hipStream_t st, int T) {
   P.d_boards = (BoardDesc*)((char*)meta + ob);
   P.d_segs = (Segment*)((char*)meta + os);
   P.d_items = (WaveItem*)((char*)meta + oi);
-  if (e == hipSuccess) e = enqueue_plan(P, st);
+  if (e == hipSuccess) e = enqueue_plan(P, st, side.st, side.fork, side.join);
   scratch_free(meta, st);
   scratch_free(scratch, st);
   rc = defer_host_free(pinned, st);
@@ -527,6 +575,8 @@ struct gol_plan {
   int device = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipStream_t side = nullptr;  // the late group's stream (default priority)
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 extern "C" {
@@ -654,6 +704,14 @@ int gol_plan_create(const gol_board* boards, int64_t n, int t_block, gol_plan** 
     p->P.d_boards = (BoardDesc*)((char*)p->meta + ob);
     p->P.d_segs = (Segment*)((char*)p->meta + os);
     p->P.d_items = (WaveItem*)((char*)p->meta + oi);
+    e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      rc = hip_error(e, "plan stream and events");
+      (void)gol_plan_destroy(p);
+      return rc;
+    }
     *out = p;
     return GOL_OK;
   } catch (const std::bad_alloc&) {
@@ -666,13 +724,13 @@ int gol_plan_run(gol_plan* p, void* stream) {
   if (!p) return set_error(GOL_EINVAL, "null plan");
   hipStream_t st = (hipStream_t)stream;
   if (st == nullptr) {
-    hipError_t e = enqueue_plan(p->P, st);
+    hipError_t e = enqueue_plan(p->P, st, p->side, p->fork, p->join);
     return e == hipSuccess ? GOL_OK : hip_error(e, "gol_plan_run");
   }
   if (!p->exec) {
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
-    hipError_t el = enqueue_plan(p->P, st);
+    hipError_t el = enqueue_plan(p->P, st, p->side, p->fork, p->join);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(st, &g);
     if (el != hipSuccess) {
@@ -707,6 +765,9 @@ int gol_plan_destroy(gol_plan* p) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->meta) (void)hipFree(p->meta);
   if (p->P.d_scratch) (void)hipFree(p->P.d_scratch);
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  if (p->join) (void)hipEventDestroy(p->join);
+  if (p->side) (void)hipStreamDestroy(p->side);
   delete p;
   return GOL_OK;
 }
@@ -723,12 +784,14 @@ int gol_set_allocator(gol_alloc_fn alloc, gol_free_fn free_fn, void* ctx) {
 
 // Host-only view of a batch schedule (no device work): used to test the
 // planner.  rows/cols/generations: n entries.  Writes up to cap_segs
-// segments and cap_items waves; returns their counts and the level sizes
-// (up to cap_levels).  Returns GOL_EINVAL on invalid boards.
+// segments and cap_items waves; returns their counts, the level sizes (up to
+// cap_levels pairs), the late group's first wave and each board's first
+// level.  Returns GOL_EINVAL on invalid boards.
 int gol_debug_plan_tables(const int64_t* rows, const int64_t* cols, const int64_t* gens, int64_t n,
                           int t_block, int band_rows, void* segs, int64_t cap_segs, void* items,
-                          int64_t cap_items, int32_t* level_items, int64_t cap_levels,
-                          int64_t* nsegs, int64_t* nitems, int64_t* nlevels) {
+                          int64_t cap_items, int32_t* levels, int64_t cap_levels,
+                          int32_t* starts, int32_t* late_begin, int64_t* nsegs, int64_t* nitems,
+                          int64_t* nlevels) {
   try {
     if (n < 0 || (n > 0 && (!rows || !cols || !gens))) return set_error(GOL_EINVAL, "bad arrays");
     std::vector<BoardReq> req((size_t)n);
@@ -747,9 +810,13 @@ int gol_debug_plan_tables(const int64_t* rows, const int64_t* cols, const int64_
     if (items)
       memcpy(items, hp.items.data(),
              std::min<size_t>(hp.items.size(), (size_t)cap_items) * sizeof(WaveItem));
-    if (level_items)
-      memcpy(level_items, hp.level_items.data(),
-             std::min<size_t>(hp.level_items.size(), (size_t)cap_levels) * sizeof(int32_t));
+    if (levels)
+      for (size_t L = 0; L < std::min<size_t>(hp.level_items.size(), (size_t)cap_levels); ++L) {
+        levels[2 * L] = hp.level_early[L];
+        levels[2 * L + 1] = hp.level_late[L];
+      }
+    if (starts) memcpy(starts, hp.start.data(), hp.start.size() * sizeof(int32_t));
+    if (late_begin) *late_begin = hp.late_begin;
     return GOL_OK;
   } catch (const std::bad_alloc&) {
     return set_error(GOL_ENOMEM, "host allocation failed");

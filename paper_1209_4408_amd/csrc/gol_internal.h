@@ -33,11 +33,11 @@ constexpr bool pass_config_compiled(int layout, int T, int pd) {
              : layout == kLayoutPaired && (T == 8 || T == 12 || T == 16) && (pd == 9 || pd == 12);
 }
 
-// One board as seen by one launch of the pass kernel.  Pass j (0-based) of
-// the board reads  src0            if j == 0,
-//                  w[(j-1+par)&1]  otherwise,
-// and writes       w[(j+par)&1].
-// Pass 0 advances Tfirst generations, every later pass the kernel's T.
+// One board as seen by one launch of the pass kernel.  The board runs pass
+// j (0-based) at level start + j.  Pass j reads  src0            if j == 0,
+//                                                w[(j-1+par)&1]  otherwise,
+// and writes                                     w[(j+par)&1].
+// Pass jshort advances Tshort generations, every other pass the kernel's T.
 struct BoardDesc {
   const uint32_t* src0;
   uint32_t* w[2];
@@ -45,8 +45,10 @@ struct BoardDesc {
   int32_t C;       // columns (cells per row)
   int32_t D;       // dwords per row = 2 * ceil(C / 64)
   int32_t K;       // passes
-  int32_t Tfirst;  // generations of pass 0, 1 <= Tfirst <= T
+  int32_t Tshort;  // generations of pass jshort, 1 <= Tshort <= T
   int32_t par;
+  int32_t start;   // level of pass 0
+  int32_t jshort;  // 0 or K - 1
 };
 
 // A run of consecutive lanes of one wave that work on one tile of one board:
@@ -69,7 +71,9 @@ struct WaveItem {
   int32_t seg_begin;
   int16_t nseg;
   uint16_t h;      // max h over its segments
-  int32_t maxK;    // the wave takes part in levels 0 .. maxK - 1
+  int32_t maxK;    // largest pass count of its boards: the wave takes part in
+                   // levels 0 .. maxK - 1 (early group) or Kmax - maxK ..
+                   // Kmax - 1 (late group)
   int32_t flags;   // kItemAligned: every lane's board has C % 32 == 0
 };
 constexpr int32_t kItemAligned = 1;

@@ -650,13 +650,17 @@ __global__ __launch_bounds__(64) void k_board_pass_half(PassArgs a, GridGeom g) 
 // ---------------------------------------------------------------------------
 // Many boards: waves from a table, each made of one or more segments.
 // ---------------------------------------------------------------------------
+// A launch runs the waves items[0, nearly) and items[late_begin,
+// late_begin + nlate) of level `level`.
 template <int TM, bool MASKED>
 __global__ __launch_bounds__(64) void k_batch_pass(const BoardDesc* __restrict__ boards,
                                                    const Segment* __restrict__ segs,
-                                                   const WaveItem* __restrict__ items, int nitems,
-                                                   int level) {
-  const int it = xcd_item(nitems);
-  if (it >= nitems) return;  // whole wave
+                                                   const WaveItem* __restrict__ items, int nearly,
+                                                   int nlate, int late_begin, int level) {
+  const int nitems = nearly + nlate;
+  const int idx = xcd_item(nitems);
+  if (idx >= nitems) return;  // whole wave
+  const int it = idx < nearly ? idx : late_begin + (idx - nearly);
   const WaveItem w = items[it];
   const int lane = (int)threadIdx.x;
   int mine = -1;
@@ -668,11 +672,12 @@ __global__ __launch_bounds__(64) void k_batch_pass(const BoardDesc* __restrict__
   if (mine >= 0) {
     const Segment sg = segs[mine];
     const BoardDesc bd = boards[sg.board];
-    const bool active = level < bd.K;
-    const int j = active ? level : bd.K - 1;
+    const int jl = level - bd.start;
+    const bool active = jl >= 0 && jl < bd.K;
+    const int j = jl < 0 ? 0 : (jl < bd.K ? jl : bd.K - 1);
     const uint32_t* src = (j == 0) ? bd.src0 : bd.w[(j - 1 + bd.par) & 1];
     uint32_t* dst = bd.w[(j + bd.par) & 1];
-    const int Tl = (j == 0) ? bd.Tfirst : TM;
+    const int Tl = (j == bd.jshort) ? bd.Tshort : TM;
     lane_setup(L, src, dst, bd.R, bd.C, bd.D, sg.p0 + (lane - sg.lane0), lane - sg.lane0,
                sg.nlanes, sg.r0, sg.h, TM, Tl, active);
   } else {
@@ -800,32 +805,37 @@ hipError_t launch_board_pass_half(int T, const uint32_t* src, uint32_t* dst, int
 
 template <int TM, bool MASKED>
 static hipError_t launch_batch_pass_t(const BoardDesc* boards, const Segment* segs,
-                                      const WaveItem* items, int nitems, int level,
-                                      hipStream_t st) {
-  const int grid = ((nitems + 7) / 8) * 8;
+                                      const WaveItem* items, int nearly, int nlate,
+                                      int late_begin, int level, hipStream_t st) {
+  const int grid = ((nearly + nlate + 7) / 8) * 8;
   hipLaunchKernelGGL((k_batch_pass<TM, MASKED>), dim3(grid), dim3(64), 0, st, boards, segs, items,
-                     nitems, level);
+                     nearly, nlate, late_begin, level);
   return hipGetLastError();
 }
 
+// Level `level` of a batch schedule: the waves items[0, nearly) and
+// items[late_begin, late_begin + nlate); masked when some pass of the level
+// is shorter than T.
 hipError_t launch_batch_pass(int T, bool masked, const BoardDesc* boards, const Segment* segs,
-                             const WaveItem* items, int nitems, int level, hipStream_t st) {
-  if (nitems <= 0) return hipSuccess;
+                             const WaveItem* items, int nearly, int nlate, int late_begin,
+                             int level, hipStream_t st) {
+  if (nearly + nlate <= 0) return hipSuccess;
+#define GOL_LAUNCH_BATCH(TV)                                                                \
+  case TV:                                                                                  \
+    return masked ? launch_batch_pass_t<TV, true>(boards, segs, items, nearly, nlate,       \
+                                                  late_begin, level, st)                    \
+                  : launch_batch_pass_t<TV, false>(boards, segs, items, nearly, nlate,      \
+                                                   late_begin, level, st);
   switch (T) {
-    case 1: return masked ? launch_batch_pass_t<1, true>(boards, segs, items, nitems, level, st)
-                          : launch_batch_pass_t<1, false>(boards, segs, items, nitems, level, st);
-    case 2: return masked ? launch_batch_pass_t<2, true>(boards, segs, items, nitems, level, st)
-                          : launch_batch_pass_t<2, false>(boards, segs, items, nitems, level, st);
-    case 4: return masked ? launch_batch_pass_t<4, true>(boards, segs, items, nitems, level, st)
-                          : launch_batch_pass_t<4, false>(boards, segs, items, nitems, level, st);
-    case 8: return masked ? launch_batch_pass_t<8, true>(boards, segs, items, nitems, level, st)
-                          : launch_batch_pass_t<8, false>(boards, segs, items, nitems, level, st);
-    case 12: return masked ? launch_batch_pass_t<12, true>(boards, segs, items, nitems, level, st)
-                           : launch_batch_pass_t<12, false>(boards, segs, items, nitems, level, st);
-    case 16: return masked ? launch_batch_pass_t<16, true>(boards, segs, items, nitems, level, st)
-                           : launch_batch_pass_t<16, false>(boards, segs, items, nitems, level, st);
+    GOL_LAUNCH_BATCH(1)
+    GOL_LAUNCH_BATCH(2)
+    GOL_LAUNCH_BATCH(4)
+    GOL_LAUNCH_BATCH(8)
+    GOL_LAUNCH_BATCH(12)
+    GOL_LAUNCH_BATCH(16)
     default: return hipErrorInvalidValue;
   }
+#undef GOL_LAUNCH_BATCH
 }
 
 static int grid_for(int64_t n, int per_block) {

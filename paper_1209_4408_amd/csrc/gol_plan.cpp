@@ -125,50 +125,15 @@ struct ItemBuild {
 };
 }  // namespace
 
-bool build_plan(const std::vector<BoardReq>& boards, int T, int band_rows, HostPlan& plan,
-                std::string& err) {
-  if (!valid_T(T)) {
-    err = "generations per pass must be 1, 2, 4, 8, 12 or 16";
-    return false;
-  }
-  if (band_rows < 1 || band_rows > 65535) {
-    err = "band height out of range";
-    return false;
-  }
-  plan = HostPlan();
-  plan.T = T;
-  plan.band_rows = band_rows;
-  const size_t n = boards.size();
-  plan.K.assign(n, 0);
-  plan.Tfirst.assign(n, 0);
-  for (size_t b = 0; b < n; ++b) {
-    const BoardReq& q = boards[b];
-    if (q.rows < 1 || q.cols < 1 || q.rows > (1 << 30) || q.cols > (1 << 30) ||
-        q.generations < 0) {
-      err = "board " + std::to_string(b) + ": size or generations out of range";
-      return false;
-    }
-    const int64_t K = (q.generations + T - 1) / T;
-    if (K > (int64_t)1 << 30) {
-      err = "board " + std::to_string(b) + ": too many generations";
-      return false;
-    }
-    plan.K[b] = (int32_t)K;
-    plan.Tfirst[b] = K > 0 ? (int32_t)(q.generations - (K - 1) * T) : 0;
-    if (K > 0 && plan.Tfirst[b] < T) plan.level0_masked = true;
-    plan.cell_updates += (double)q.rows * (double)q.cols * (double)q.generations;
-  }
-  std::vector<int32_t> order;
-  for (size_t b = 0; b < n; ++b)
-    if (plan.K[b] > 0) order.push_back((int32_t)b);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t a, int32_t c) { return plan.K[a] > plan.K[c]; });
-
-  // First-fit packing of segments into 64-lane waves.  A segment joins an
-  // open wave if it fits, its band is at most an eighth shorter than the
-  // wave's tallest (the wave's row count is its tallest band), and its board
-  // needs at most max(2, maxK / 8) fewer passes than the wave's longest board
-  // (lanes of boards that finish early idle in later levels).
+// First-fit packing of the segments of `order`'s boards (K descending) into
+// 64-lane waves.  A segment joins an open wave if it fits, its band is at
+// most an eighth shorter than the wave's tallest (the wave's row count is its
+// tallest band), and its board needs at most max(2, maxK / 8) fewer passes
+// than the wave's longest board (lanes of shorter boards idle in the levels
+// where their board does not run).
+static std::vector<ItemBuild> pack_waves(const std::vector<BoardReq>& boards,
+                                         const std::vector<int32_t>& K,
+                                         const std::vector<int32_t>& order, int band_rows) {
   std::vector<ItemBuild> built;
   std::vector<size_t> open;  // indices of waves that may still take segments
   for (int32_t b : order) {
@@ -178,7 +143,7 @@ bool build_plan(const std::vector<BoardReq>& boards, int T, int band_rows, HostP
     const Split S = split(D, ns);
     const int64_t nb = (q.rows + band_rows - 1) / band_rows;
     const Split B = split(q.rows, nb);
-    const int Kb = plan.K[b];
+    const int Kb = K[b];
     const bool aligned = (q.cols % 32) == 0;
     // waves that can no longer take boards of this K close for good
     open.erase(std::remove_if(open.begin(), open.end(),
@@ -223,26 +188,107 @@ bool build_plan(const std::vector<BoardReq>& boards, int T, int band_rows, HostP
   }
   std::stable_sort(built.begin(), built.end(),
                    [](const ItemBuild& a, const ItemBuild& c) { return a.maxK > c.maxK; });
+  return built;
+}
+
+bool build_plan(const std::vector<BoardReq>& boards, int T, int band_rows, HostPlan& plan,
+                std::string& err) {
+  if (!valid_T(T)) {
+    err = "generations per pass must be 1, 2, 4, 8, 12 or 16";
+    return false;
+  }
+  if (band_rows < 1 || band_rows > 65535) {
+    err = "band height out of range";
+    return false;
+  }
+  plan = HostPlan();
+  plan.T = T;
+  plan.band_rows = band_rows;
+  const size_t n = boards.size();
+  plan.K.assign(n, 0);
+  plan.Tshort.assign(n, 0);
+  plan.start.assign(n, 0);
+  plan.jshort.assign(n, 0);
+  for (size_t b = 0; b < n; ++b) {
+    const BoardReq& q = boards[b];
+    if (q.rows < 1 || q.cols < 1 || q.rows > (1 << 30) || q.cols > (1 << 30) ||
+        q.generations < 0) {
+      err = "board " + std::to_string(b) + ": size or generations out of range";
+      return false;
+    }
+    const int64_t K = (q.generations + T - 1) / T;
+    if (K > (int64_t)1 << 30) {
+      err = "board " + std::to_string(b) + ": too many generations";
+      return false;
+    }
+    plan.K[b] = (int32_t)K;
+    plan.Tshort[b] = K > 0 ? (int32_t)(q.generations - (K - 1) * T) : 0;
+    plan.cell_updates += (double)q.rows * (double)q.cols * (double)q.generations;
+  }
+  std::vector<int32_t> order;
+  for (size_t b = 0; b < n; ++b)
+    if (plan.K[b] > 0) order.push_back((int32_t)b);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t c) { return plan.K[a] > plan.K[c]; });
+  const int Kmax = order.empty() ? 0 : plan.K[order.front()];
+
+  // Groups: longest boards first, each to the group (early: levels 0 .. K - 1,
+  // late: Kmax - K .. Kmax - 1) whose levels it spans hold less work so far.
+  // A board's work per pass is counted as its lanes times its rows.
+  std::vector<double> load((size_t)Kmax, 0.0), prefix((size_t)Kmax + 1, 0.0);
+  std::vector<int32_t> early, late;
+  for (int32_t b : order) {
+    const int Kb = plan.K[b];
+    const double w = (double)boards[b].rows * (double)(dwords_per_row(boards[b].cols) + 2);
+    double e = 0.0, l = 0.0;
+    for (int L = 0; L < Kb; ++L) e += load[L];
+    for (int L = Kmax - Kb; L < Kmax; ++L) l += load[L];
+    if (l < e) {
+      late.push_back(b);
+      plan.start[b] = Kmax - Kb;
+      plan.jshort[b] = Kb - 1;
+      for (int L = Kmax - Kb; L < Kmax; ++L) load[L] += w;
+    } else {
+      early.push_back(b);
+      for (int L = 0; L < Kb; ++L) load[L] += w;
+    }
+  }
+
+  const std::vector<ItemBuild> be = pack_waves(boards, plan.K, early, band_rows);
+  const std::vector<ItemBuild> bl = pack_waves(boards, plan.K, late, band_rows);
   plan.segs.clear();
   plan.items.clear();
-  plan.items.reserve(built.size());
-  for (const ItemBuild& it : built) {
-    WaveItem w;
-    w.seg_begin = (int32_t)plan.segs.size();
-    w.nseg = (int16_t)it.segs.size();
-    w.h = (uint16_t)it.h;
-    w.maxK = it.maxK;
-    w.flags = it.aligned ? kItemAligned : 0;
-    plan.items.push_back(w);
-    plan.segs.insert(plan.segs.end(), it.segs.begin(), it.segs.end());
+  plan.items.reserve(be.size() + bl.size());
+  for (const std::vector<ItemBuild>* grp : {&be, &bl}) {
+    if (grp == &bl) plan.late_begin = (int32_t)plan.items.size();
+    for (const ItemBuild& it : *grp) {
+      WaveItem w;
+      w.seg_begin = (int32_t)plan.segs.size();
+      w.nseg = (int16_t)it.segs.size();
+      w.h = (uint16_t)it.h;
+      w.maxK = it.maxK;
+      w.flags = it.aligned ? kItemAligned : 0;
+      plan.items.push_back(w);
+      plan.segs.insert(plan.segs.end(), it.segs.begin(), it.segs.end());
+    }
   }
-  const int Kmax = built.empty() ? 0 : built.front().maxK;
+  plan.level_early.assign(Kmax, 0);
+  plan.level_late.assign(Kmax, 0);
   plan.level_items.assign(Kmax, 0);
-  size_t cnt = plan.items.size();
+  for (int32_t b : early)
+    if (plan.Tshort[b] < T) plan.early_masked = true;
+  for (int32_t b : late)
+    if (plan.Tshort[b] < T) plan.late_masked = true;
+  // early waves with maxK > L run at level L; late waves with maxK >= Kmax - L
+  size_t ce = be.size(), cl = 0;
   for (int L = 0; L < Kmax; ++L) {
-    while (cnt > 0 && plan.items[cnt - 1].maxK <= L) --cnt;
-    plan.level_items[L] = (int32_t)cnt;
-    for (size_t i = 0; i < cnt; ++i) plan.lane_steps += (double)kWave * (plan.items[i].h + 2 * T);
+    while (ce > 0 && be[ce - 1].maxK <= L) --ce;
+    while (cl < bl.size() && bl[cl].maxK >= Kmax - L) ++cl;
+    plan.level_early[L] = (int32_t)ce;
+    plan.level_late[L] = (int32_t)cl;
+    plan.level_items[L] = (int32_t)(ce + cl);
+    for (size_t i = 0; i < ce; ++i) plan.lane_steps += (double)kWave * (be[i].h + 2 * T);
+    for (size_t i = 0; i < cl; ++i) plan.lane_steps += (double)kWave * (bl[i].h + 2 * T);
   }
   return true;
 }

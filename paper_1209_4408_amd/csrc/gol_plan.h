@@ -1,18 +1,23 @@
 // Host-side schedule of tile passes for one or many boards (no HIP calls).
 //
-// A board of G generations runs K = ceil(G / T) passes: pass 0 advances
-// G - (K - 1) T generations, every later pass T.  Boards run their passes
-// level by level: level L holds pass L of every board with K > L, so one
-// launch per level advances all boards still running, and a board that
-// needs fewer generations simply drops out of later levels.
+// A board of G generations runs K = ceil(G / T) passes: one of them (the
+// first or the last) advances G - (K - 1) T generations, every other T.
+// Passes run level by level, one launch per level, Kmax = max K levels.  A
+// board of the early group runs its passes at levels 0 .. K - 1 (the short
+// one first), a board of the late group at levels Kmax - K .. Kmax - 1 (the
+// short one last), so each launch carries a similar amount of work instead
+// of the last levels holding only the few longest boards, whose passes then
+// run one wave per SIMD.  Boards are assigned longest first, each to the
+// group whose levels it would span hold less work so far.
 //
 // Tiles: a board's row of D dwords is cut into strips of at most 62 useful
 // dwords (each strip + 2 halo lanes fits a 64-lane wave), its rows into bands
 // of at most `band_rows` rows.  A tile is one segment of consecutive lanes.
 // Tiles of 32 lanes or more get a wave of their own; smaller ones (narrow
 // boards) are packed several to a wave, grouped by band height and by K so
-// that packed lanes stay busy.  Waves are sorted by their largest K, so the
-// waves of level L are a prefix of one array.
+// that packed lanes stay busy.  Each group's waves are sorted by their
+// largest K, so the waves of level L are a prefix of the early group's array
+// followed by a prefix of the late group's.
 #pragma once
 #include <stdint.h>
 
@@ -31,11 +36,17 @@ struct HostPlan {
   int T = 8;
   int band_rows = 64;
   std::vector<Segment> segs;
-  std::vector<WaveItem> items;
-  std::vector<int32_t> level_items;  // waves taking part in level L
+  std::vector<WaveItem> items;       // early group, then late group
+  int32_t late_begin = 0;            // index of the late group's first wave
+  std::vector<int32_t> level_early;  // level L launches items [0, level_early[L])
+  std::vector<int32_t> level_late;   // and [late_begin, late_begin + level_late[L])
+  std::vector<int32_t> level_items;  // waves taking part in level L (the sum)
+  bool early_masked = false;         // level 0 of the early group has a pass shorter than T
+  bool late_masked = false;          // the late group's last level has one
   std::vector<int32_t> K;            // passes per board
-  std::vector<int32_t> Tfirst;       // generations of pass 0 per board
-  bool level0_masked = false;        // some board's pass 0 is shorter than T
+  std::vector<int32_t> Tshort;       // generations of the board's short pass
+  std::vector<int32_t> start;        // level of the board's pass 0
+  std::vector<int32_t> jshort;       // index of the short pass: 0 or K - 1
   double cell_updates = 0;           // sum rows * cols * generations
   double lane_steps = 0;             // sum over levels of waves * 64 * row steps
 };

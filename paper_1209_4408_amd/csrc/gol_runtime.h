@@ -66,6 +66,19 @@ struct DevicePlan {
 
 int plan_boards(const gol_board* boards, int64_t n, int T, int band_rows, DevicePlan& P);
 void fill_board_descs(DevicePlan& P);
-hipError_t enqueue_plan(const DevicePlan& P, hipStream_t st);
+
+// Queues the level launches of a batch schedule whose tables are on the
+// device: the early group's levels on `st`, the late group's on `side`,
+// which first waits (through `fork`) for the work queued on `st` so far;
+// then `st` waits (through `join`) for `side`.  The groups hold different
+// boards, so the two streams' launches overlap and each fills the tail of
+// the other's levels.  With no late group everything goes on `st` and the
+// events are not used.  `side` must have the default priority.
+hipError_t enqueue_levels(const HostPlan& hp, const BoardDesc* boards, const Segment* segs,
+                          const WaveItem* items, hipStream_t st, hipStream_t side,
+                          hipEvent_t fork, hipEvent_t join);
+// The normalising copies of a plan, then enqueue_levels.
+hipError_t enqueue_plan(const DevicePlan& P, hipStream_t st, hipStream_t side, hipEvent_t fork,
+                        hipEvent_t join);
 
 }  // namespace gol

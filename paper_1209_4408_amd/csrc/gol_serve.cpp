@@ -46,9 +46,6 @@
 
 namespace gol {
 
-hipError_t launch_batch_pass(int T, bool masked, const BoardDesc* boards, const Segment* segs,
-                             const WaveItem* items, int nitems, int level, hipStream_t st);
-
 namespace {
 
 // Opaque marker of queued device work; done() says whether it has run.
@@ -123,6 +120,7 @@ class HipExec : public Exec {
     sync();
     reap();
     if (compute_) (void)hipStreamDestroy(compute_);
+    if (compute2_) (void)hipStreamDestroy(compute2_);
     if (copy_) (void)hipStreamDestroy(copy_);
   }
   int init() {
@@ -130,6 +128,7 @@ class HipExec : public Exec {
     (void)hipGetDevice(&prev);
     hipError_t e = hipSetDevice(dev_);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&compute_, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&compute2_, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking);
     if (e == hipSuccess) {
       hipMemPool_t pool;
@@ -200,9 +199,12 @@ class HipExec : public Exec {
     const BoardDesc* d_b = (const BoardDesc*)meta;
     const Segment* d_s = (const Segment*)((char*)meta + os);
     const WaveItem* d_i = (const WaveItem*)((char*)meta + oi);
-    for (size_t L = 0; L < hp.level_items.size() && e == hipSuccess; ++L)
-      e = launch_batch_pass(hp.T, L == 0 && hp.level0_masked, d_b, d_s, d_i, hp.level_items[L],
-                            (int)L, compute_);
+    hipEvent_t fork = nullptr, join = nullptr;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+    if (e == hipSuccess) e = enqueue_levels(hp, d_b, d_s, d_i, compute_, compute2_, fork, join);
+    if (fork) (void)hipEventDestroy(fork);  // the waits on them are queued
+    if (join) (void)hipEventDestroy(join);
     (void)hipFreeAsync(meta, compute_);
     if (e == hipSuccess) e = hipEventRecord(c->end, compute_);
     if (e != hipSuccess) {
@@ -283,6 +285,7 @@ class HipExec : public Exec {
   };
   int dev_;
   hipStream_t compute_ = nullptr, copy_ = nullptr;
+  hipStream_t compute2_ = nullptr;  // the late group of each chunk's schedule
   PinnedPool pool_;
   std::vector<Pending> pending_;  // touched by the scheduler thread under the server lock
 };
@@ -318,7 +321,7 @@ class HostExec : public Exec {
   int run_chunk(const std::vector<BoardDesc>& bd, const HostPlan& hp, Token* done) override {
     if (++chunks_ == fail_at_) return set_error(GOL_EDEVICE, "host executor: injected failure");
     for (const BoardDesc& d : bd) {
-      const uint64_t g = (uint64_t)(d.K - 1) * (uint64_t)hp.T + (uint64_t)d.Tfirst;
+      const uint64_t g = (uint64_t)(d.K - 1) * (uint64_t)hp.T + (uint64_t)d.Tshort;
       const uint64_t* src = (const uint64_t*)d.src0;
       uint64_t* dst = (uint64_t*)d.w[(d.K - 1 + d.par) & 1];
       const size_t words = (size_t)d.R * (size_t)(d.D / 2);
@@ -504,7 +507,9 @@ static int queue_chunk(Server& S, std::vector<uint64_t>& retire_now) {
     d.C = (int32_t)r.cols;
     d.D = (int32_t)(2 * r.W);
     d.K = hp.K[b];
-    d.Tfirst = hp.Tfirst[b];
+    d.Tshort = hp.Tshort[b];
+    d.start = hp.start[b];
+    d.jshort = hp.jshort[b];
     d.src0 = (const uint32_t*)r.d_buf[r.cur];
     d.w[0] = (uint32_t*)r.d_buf[r.cur ^ 1];
     d.w[1] = (uint32_t*)r.d_buf[r.cur];

@@ -79,13 +79,15 @@ def test_set_allocator_pairs():
 # Planner
 # ---------------------------------------------------------------------------
 def check_plan(rows, cols, gens, T, band):
-    segs, items, levels = gol.plan_tables(rows, cols, gens, T, band)
+    segs, items, levels, late_begin, starts = gol.plan_tables(rows, cols, gens, T, band)
     n = len(rows)
     K = [(g + T - 1) // T for g in gens]
+    Kmax = max(K) if K else 0
     # every useful (row, dword) of every running board is written by exactly one lane
     cover = {b: np.zeros((rows[b], 2 * ((cols[b] + 63) // 64)), np.int32) for b in range(n)
              if K[b] > 0}
-    for it in items:
+    for i, it in enumerate(items):
+        late = i >= late_begin
         lanes = 0
         ss = segs[it["seg_begin"]: it["seg_begin"] + it["nseg"]]
         assert it["nseg"] >= 1
@@ -96,6 +98,8 @@ def check_plan(rows, cols, gens, T, band):
             assert s["nlanes"] >= 3 and s["h"] >= 1 and s["h"] <= it["h"]
             b = int(s["board"])
             mk = max(mk, K[b])
+            # a board of the late group ends at the last level, one of the early starts at 0
+            assert starts[b] == (Kmax - K[b] if late else 0), (b, late, starts[b])
             D = 2 * ((cols[b] + 63) // 64)
             useful = np.arange(s["p0"] + 1, s["p0"] + s["nlanes"] - 1)
             assert useful.min() >= 0 and useful.max() < D
@@ -106,12 +110,14 @@ def check_plan(rows, cols, gens, T, band):
         assert it["maxK"] == mk
     for b, c in cover.items():
         assert (c == 1).all(), f"board {b} not covered exactly once"
-    # waves sorted by levels, level L launches the waves with maxK > L (a prefix)
-    mk = items["maxK"]
-    assert (np.diff(mk) <= 0).all()
-    assert len(levels) == (max(K) if K else 0)
-    for L, cnt in enumerate(levels):
-        assert cnt == int((mk > L).sum())
+    # each group's waves sorted by pass count; level L launches a prefix of each:
+    # early waves with maxK > L, late waves with maxK >= Kmax - L
+    me, ml = items["maxK"][:late_begin], items["maxK"][late_begin:]
+    assert (np.diff(me) <= 0).all() and (np.diff(ml) <= 0).all()
+    assert len(levels) == Kmax
+    for L, (ce, cl) in enumerate(levels):
+        assert ce == int((me > L).sum())
+        assert cl == int((ml >= Kmax - L).sum())
     return segs, items, levels
 
 
@@ -133,6 +139,10 @@ def test_plan_batched_mix_shape():
     segs, items, levels = check_plan(rows, cols, gens, 8, 64)
     lanes_used = sum(int(s["nlanes"]) for s in segs)
     assert lanes_used / (64 * len(items)) > 0.7  # narrow boards share waves
+    # early and late groups keep every level busy: without them the last levels
+    # would hold only the few longest boards
+    per_level = levels.sum(axis=1)
+    assert per_level.min() > 0.5 * per_level.mean(), per_level
 
 
 def test_plan_rejects_bad_input():
