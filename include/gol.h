@@ -137,9 +137,13 @@ int gol_unpack(const uint64_t* d_packed, int64_t rows, int64_t cols, uint8_t* d_
 
 /*
  * Many independent boards, each with its own size and generation count, in
- * one schedule of tile passes (uneven sizes share waves; boards that need
- * more generations keep running while finished ones drop out).
- * d_in / d_out follow gol_step_packed's rules per board.  Asynchronous.
+ * one schedule of tile passes (uneven sizes share waves; a board runs its
+ * passes in a block of consecutive levels, the boards being split between
+ * levels at the start and at the end of the schedule so every level carries
+ * a similar load).  d_in / d_out follow gol_step_packed's rules per board.
+ * Asynchronous on `stream`: the two halves of the schedule run on `stream`
+ * and on a library stream that waits for `stream`'s earlier work and that
+ * `stream` waits for in turn, so the work is ordered on `stream` as one call.
  */
 typedef struct {
   const uint64_t* d_in;
