@@ -462,7 +462,7 @@ def main():
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=2700.0,
                     help="Poisson arrival rate; requests average 1.08e10 cell-updates, so "
-                         "2700/s offers 2.9e13 cell-updates/s, about 0.6 of the batched capacity")
+                         "2700/s offers 2.9e13 cell-updates/s, about half the batched capacity")
     ap.add_argument("--chunk", type=int, default=240)
     ap.add_argument("--plain-requests", type=int, default=4096)
     ap.add_argument("--boards", type=int, default=4096)
