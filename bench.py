@@ -10,7 +10,9 @@ Other workloads (--workload): c1 (256^2 byte board, 100 generations, host
 API), c3 (65536^2, 200 generations, temporal-blocked vs one generation per
 launch), c4 (4096 boards in one batched schedule vs one launch sequence per
 board), c5 (Poisson request stream through the continuous-batching server vs
-a one-at-a-time server).
+a one-at-a-time server), pop (population counting: the kernel on the 65536^2
+board and Table 1's checks on the 16384^2 run), copy (copy-kernel calibration
+of the traffic counters).
 """
 from __future__ import annotations
 
@@ -425,6 +427,72 @@ def copy_calibration(args):
                       "read_plus_write_GBps": 2 * R * C / 8 / dt / 1e9}), flush=True)
 
 
+def population_workload(args):
+    """Population (live cells, the paper's Table 1 quantity): the counting
+    kernel alone on the 65536^2 board (HBM-bound: it reads the board once),
+    and the 16384^2 run of 1000 generations with the population recorded at
+    Table 1's iteration counts (100, 200, 500, 1000) against the same run
+    without."""
+    import torch
+    import paper_1209_4408_amd as gol
+    import seeded_inputs
+    R = C = 65536
+    w = seeded_inputs.board_packed(SEED, 0, R, C, 0.5)
+    d = torch.from_numpy(w.view(np.int64)).cuda()
+    del w
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st = torch.cuda.current_stream()
+    for _ in range(args.warmup + 1):
+        gol.lib().gol_population(d.data_ptr(), R, C, cnt.data_ptr(), st.cuda_stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        gol.lib().gol_population(d.data_ptr(), R, C, cnt.data_ptr(), st.cuda_stream)
+    e1.record(st)
+    torch.cuda.synchronize()
+    dt = e0.elapsed_time(e1) / 1e3 / args.steps
+    bytes_ = R * C // 8
+    line = {"metric": "cells counted/sec", "value": R * C / dt, "unit": "cells/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+            "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "population of a 65536x65536 bit-packed board, "
+                                   "Bernoulli(0.5), seed 1209", "population": int(cnt.item())},
+            "roofline": {"bound": "hbm", "achieved": bytes_ / dt / 1e9, "peak": 8000.0,
+                         "unit": "GB/s", "frac": bytes_ / dt / 8e12, "traffic": None,
+                         "kernel": "k_population", "bytes_per_launch": bytes_}}
+    del d
+    torch.cuda.empty_cache()
+    # Table 1's checks on the benchmark board
+    R = C = 16384
+    G = 1000
+    w = seeded_inputs.board_packed(SEED, 0, R, C, 0.3)
+    d_in = torch.from_numpy(w.view(np.int64)).cuda()
+    d_out = torch.empty_like(d_in)
+    cfg = gol.tune_config(R, C)
+    checks = [100, 200, 500, 1000]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(args.steps):
+            fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3 / args.steps
+    t_plain = timed(lambda: gol.step_packed(d_in, R, C, G, d_out, config=cfg))
+    out = {}
+    t_pop = timed(lambda: out.update(c=gol.step_packed_population(d_in, R, C, G, checks,
+                                                                   d_out=d_out, config=cfg)[1]))
+    line["table1_checks"] = {"board": "16384x16384, p 0.3, seed 1209, 1000 generations",
+                             "checks": checks, "population": out["c"].cpu().tolist(),
+                             "ms_with_checks": t_pop * 1e3, "ms_without": t_plain * 1e3,
+                             "overhead": t_pop / t_plain - 1.0}
+    print(json.dumps(line), flush=True)
+
+
 def sweep(args):
     """Single-board tuning sweep: generations per pass x band count x prefetch.
     Band counts put the wave total just under a multiple of the SIMD count."""
@@ -458,7 +526,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "copy"])
+    ap.add_argument("--workload", default="c2",
+                    choices=["c1", "c2", "c3", "c4", "c5", "copy", "pop"])
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=2700.0,
                     help="Poisson arrival rate; requests average 1.08e10 cell-updates, so "
@@ -521,6 +590,9 @@ def main():
                     "[32, 8192], p U(0.05, 0.7), generations U{1..10000}, 64 GiB budget")
     elif args.workload == "copy":
         copy_calibration(args)
+        return
+    elif args.workload == "pop":
+        population_workload(args)
         return
     ms = res["wall_s"] / args.steps * 1e3
     line = {

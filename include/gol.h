@@ -115,6 +115,31 @@ int gol_step_packed_cfg(const uint64_t* d_in, int64_t rows, int64_t cols, int64_
                         uint64_t* d_out, void* stream, const gol_pass_config* config);
 
 /*
+ * Population: the number of live cells, the quantity the paper tabulates at
+ * chosen iteration counts (Table 1).  Padding bits are not counted.
+ *
+ * gol_population: d_packed (device, rows * W words) -> *d_count (device
+ * int64).  Asynchronous on `stream`; reads the board once.
+ *
+ * gol_step_packed_population: gol_step_packed_cfg that also records the
+ * population after each of `ncheck` generation counts.  checks: HOST array,
+ * non-decreasing, each in 0 .. generations (repeats allowed).  d_counts:
+ * DEVICE int64[ncheck]; d_counts[i] receives the population after checks[i]
+ * generations.  A pass ends at every checked generation and the board it
+ * leaves is counted (one read of the board per check).  Asynchronous on
+ * `stream`: checks is read during the call, d_counts is written by the
+ * queued work.  Errors:
+ * GOL_EINVAL for a null array with ncheck > 0, ncheck < 0 or checks out of
+ * order or range, in addition to gol_step_packed_cfg's.
+ */
+int gol_population(const uint64_t* d_packed, int64_t rows, int64_t cols, int64_t* d_count,
+                   void* stream);
+int gol_step_packed_population(const uint64_t* d_in, int64_t rows, int64_t cols,
+                               int64_t generations, uint64_t* d_out, void* stream,
+                               const gol_pass_config* config, const int64_t* checks,
+                               int64_t ncheck, int64_t* d_counts);
+
+/*
  * Autotuner of the single-board path: times candidate launch configurations
  * (both layouts, t_block 8, 12 and 16, several band heights) for rows x cols
  * boards on the current device, using two scratch boards of that size from

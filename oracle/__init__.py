@@ -13,7 +13,8 @@ Contents:
   * ``pack`` / ``unpack``: the packed-board layout of the library boundary
     (cell (r, c) is bit c mod 64 of word r * W + c // 64, LSB first,
     W = ceil(C / 64), padding bits 0), written with ``numpy.packbits``;
-  * ``torus_window``: a wrapped sub-board, for light-cone checks of large runs.
+  * ``torus_window``: a wrapped sub-board, for light-cone checks of large runs;
+  * ``population_at``: live cells after chosen generation counts (Table 1).
 """
 from __future__ import annotations
 
@@ -156,3 +157,19 @@ def light_cone_check(gpu_out_window: np.ndarray, board_in, cols_or_none, r0: int
     res = life(win, G, threads=threads)
     centre = res[G:G + k_rows, G:G + k_cols]
     return bool(np.array_equal(centre, np.asarray(gpu_out_window, dtype=np.uint8)))
+
+
+def population_at(board: np.ndarray, checks, threads: int = 1) -> list[int]:
+    """Live cells after each generation count in ``checks`` (non-decreasing):
+    the quantity the paper tabulates at chosen iteration counts (Table 1).
+    The board is evolved with ``life`` from one check to the next and its live
+    cells counted."""
+    out, cur, g = [], board, 0
+    for c in checks:
+        c = int(c)
+        if c < g:
+            raise ValueError("checks must be non-decreasing")
+        cur = life(cur, c - g, threads)
+        g = c
+        out.append(int(np.count_nonzero(cur)))
+    return out

@@ -89,6 +89,9 @@ def lib():
             "gol_tune": (c_int, [i64, i64, vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
             "gol_step_packed_cfg": (c_int, [vp, i64, i64, i64, vp, vp,
                                             ctypes.POINTER(PassConfig)]),
+            "gol_step_packed_population": (c_int, [vp, i64, i64, i64, vp, vp,
+                                                   ctypes.POINTER(PassConfig), vp, i64, vp]),
+            "gol_population": (c_int, [vp, i64, i64, vp, vp]),
             "gol_tune_cfg": (c_int, [i64, i64, vp, ctypes.POINTER(PassConfig)]),
             "gol_pack": (c_int, [vp, i64, i64, vp, vp]),
             "gol_unpack": (c_int, [vp, i64, i64, vp, vp]),
@@ -190,6 +193,32 @@ def step_packed(d_in, rows: int, cols: int, generations: int, d_out=None, stream
         _check(lib().gol_step_packed_ex(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
                                         _stream_handle(stream), int(t_block)))
     return d_out
+
+
+def population(d_packed, rows: int, cols: int, stream=None) -> int:
+    """Live cells of a packed device board (waits for the result)."""
+    import torch
+    cnt = torch.zeros(1, dtype=torch.int64, device=d_packed.device)
+    _check(lib().gol_population(_ptr(d_packed), rows, cols, _ptr(cnt), _stream_handle(stream)))
+    return int(cnt.item())
+
+
+def step_packed_population(d_in, rows: int, cols: int, generations: int, checks, d_out=None,
+                           stream=None, config: dict | None = None):
+    """step_packed that also records the population after each generation count
+    in `checks` (non-decreasing, each in 0..generations).  Returns (d_out, counts),
+    counts a device int64 tensor with one entry per check (asynchronous)."""
+    import torch
+    if d_out is None:
+        d_out = empty_packed(rows, cols, d_in.device)
+    ch = np.ascontiguousarray(list(checks), dtype=np.int64)
+    counts = torch.empty(max(1, len(ch)), dtype=torch.int64, device=d_in.device)
+    c = PassConfig(**{k: int(v) for k, v in (config or {}).items()})
+    _check(lib().gol_step_packed_population(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
+                                            _stream_handle(stream), ctypes.byref(c),
+                                            ch.ctypes.data if len(ch) else None, len(ch),
+                                            _ptr(counts)))
+    return d_out, counts[:len(ch)]
 
 
 def tune(rows: int, cols: int, stream=None) -> tuple[int, int]:

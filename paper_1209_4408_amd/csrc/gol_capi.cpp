@@ -27,6 +27,9 @@ hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t 
                              int32_t D, const GridGeom& g, int pd, hipStream_t st);
 hipError_t launch_board_pass_half(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
                                   int32_t D, const GridGeom& g, int pd, hipStream_t st);
+hipError_t launch_population(const uint64_t* b, int64_t R, int64_t C, unsigned long long* out,
+                             hipStream_t st);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
 hipError_t launch_batch_pass(int T, bool masked, const BoardDesc* boards, const Segment* segs,
                              const WaveItem* items, int nearly, int nlate, int late_begin,
                              int level, hipStream_t st);
@@ -249,10 +252,18 @@ hipError_t launch_pass(const PassConfig& c, const uint32_t* src, uint32_t* dst, 
 }
 
 int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t* d_out,
-                hipStream_t st, const PassConfig& cfg) {
+                hipStream_t st, const PassConfig& cfg, const int64_t* checks, int64_t ncheck,
+                int64_t* d_counts) {
   int rc = check_board(R, C, G);
   if (rc) return rc;
   if (!d_in || !d_out) return set_error(GOL_EINVAL, "null board pointer");
+  if (ncheck < 0 || (ncheck > 0 && (!checks || !d_counts)))
+    return set_error(GOL_EINVAL, "population checks: null array or negative count");
+  for (int64_t i = 0; i < ncheck; ++i)
+    if (checks[i] < 0 || checks[i] > G || (i > 0 && checks[i] < checks[i - 1]))
+      return set_error(GOL_EINVAL,
+                       "population checks must be non-decreasing generation counts in 0..%lld",
+                       (long long)G);
   PassConfig c;
   rc = resolve_config(R, C, cfg, &c);
   if (rc) return rc;
@@ -261,12 +272,34 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
   if (ranges_partially_overlap(d_in, d_out, bytes))
     return set_error(GOL_EINVAL, "d_in and d_out partially overlap");
   reap_deferred(false);
-  if (G == 0) {
-    hipError_t e = launch_copy_clear_padding(d_in, R, C, d_out, st);
+  unsigned long long* counts = (unsigned long long*)d_counts;
+  hipError_t e = hipSuccess;
+  if (ncheck > 0) e = launch_fill_u32((uint32_t*)d_counts, 2 * ncheck, 0u, st);
+  // Operations in order: a pass of T > 0 generations, or (T == 0) a count of
+  // the current board into slot `slot`.  A pass ends at every checked
+  // generation, and the board it leaves is counted (one read of the board).
+  struct Op {
+    int T;
+    int64_t slot;
+  };
+  std::vector<Op> ops;
+  int64_t g = 0;
+  for (int64_t i = 0; i <= ncheck; ++i) {
+    const int64_t upto = i < ncheck ? checks[i] : G;
+    if (upto > g) {
+      for (int t : single_board_passes(upto - g, c.T)) ops.push_back(Op{t, -1});
+      g = upto;
+    }
+    if (i < ncheck) ops.push_back(Op{0, i});
+  }
+  int K = 0;
+  for (const Op& o : ops) K += o.T > 0;
+  if (K == 0) {
+    if (e == hipSuccess) e = launch_copy_clear_padding(d_in, R, C, d_out, st);
+    for (const Op& o : ops)
+      if (e == hipSuccess) e = launch_population(d_out, R, C, counts + o.slot, st);
     return e == hipSuccess ? GOL_OK : hip_error(e, "copy kernel launch");
   }
-  const std::vector<int> passes = single_board_passes(G, c.T);
-  const int K = (int)passes.size();
   void* s1v = nullptr;
   rc = scratch_alloc(&s1v, bytes, st);
   if (rc) return rc;
@@ -275,27 +308,35 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
   const uint32_t* src0 = (const uint32_t*)d_in;
   uint32_t* w[2] = {out, s1};
   int par = (K - 1) & 1;
-  hipError_t e = hipSuccess;
-  if ((const void*)d_in == (const void*)d_out && (K & 1)) {
+  if (e == hipSuccess && (const void*)d_in == (const void*)d_out && (K & 1)) {
     // pass 0 must not write the board it reads: start from a copy
     e = launch_copy_clear_padding(d_in, R, C, (uint64_t*)s1, st);
     src0 = s1;
     par = 0;
   }
-  for (int j = 0; j < K && e == hipSuccess; ++j) {
+  const uint32_t* cur = src0;  // the board after the passes so far
+  int j = 0;
+  for (const Op& o : ops) {
+    if (e != hipSuccess) break;
+    if (o.T == 0) {
+      e = launch_population((const uint64_t*)cur, R, C, counts + o.slot, st);
+      continue;
+    }
     const uint32_t* src = (j == 0) ? src0 : w[(j - 1 + par) & 1];
     uint32_t* dst = w[(j + par) & 1];
-    if (passes[j] == c.T) {
+    if (o.T == c.T) {
       e = launch_pass(c, src, dst, R, C, st);
     } else {
       // the G mod T remainder: shorter passes, one band per wave, defaults
       PassConfig r;
-      r.T = passes[j];
+      r.T = o.T;
       r.layout = kLayoutBand;
       r.pd = default_prefetch(r.T);
       r.band_rows = default_band_rows(R, C, r.T, simd_count());
       e = launch_pass(r, src, dst, R, C, st);
     }
+    cur = dst;
+    ++j;
   }
   scratch_free(s1v, st);
   if (e != hipSuccess) return hip_error(e, "tile pass launch");
@@ -624,6 +665,38 @@ int gol_step_packed_cfg(const uint64_t* d_in, int64_t rows, int64_t cols, int64_
   } catch (...) {
     return set_error(GOL_EDEVICE, "unexpected exception");
   }
+}
+
+int gol_step_packed_population(const uint64_t* d_in, int64_t rows, int64_t cols,
+                               int64_t generations, uint64_t* d_out, void* stream,
+                               const gol_pass_config* config, const int64_t* checks,
+                               int64_t ncheck, int64_t* d_counts) {
+  try {
+    PassConfig cfg;
+    if (config) {
+      cfg.T = config->t_block;
+      cfg.band_rows = config->band_rows;
+      cfg.pd = config->prefetch;
+      cfg.layout = config->layout;
+    }
+    return step_packed(d_in, rows, cols, generations, d_out, (hipStream_t)stream, cfg, checks,
+                       ncheck, d_counts);
+  } catch (const std::bad_alloc&) {
+    return set_error(GOL_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(GOL_EDEVICE, "unexpected exception");
+  }
+}
+
+int gol_population(const uint64_t* d_packed, int64_t rows, int64_t cols, int64_t* d_count,
+                   void* stream) {
+  int rc = check_board(rows, cols, 0);
+  if (rc) return rc;
+  if (!d_packed || !d_count) return set_error(GOL_EINVAL, "null pointer");
+  hipError_t e = launch_fill_u32((uint32_t*)d_count, 2, 0u, (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = launch_population(d_packed, rows, cols, (unsigned long long*)d_count, (hipStream_t)stream);
+  return e == hipSuccess ? GOL_OK : hip_error(e, "population kernel launch");
 }
 
 int gol_step_packed(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t generations,

@@ -46,8 +46,11 @@ int resolve_config(int64_t R, int64_t C, const PassConfig& want, PassConfig* out
 hipError_t launch_pass(const PassConfig& c, const uint32_t* src, uint32_t* dst, int64_t R,
                        int64_t C, hipStream_t st);
 
+// checks (host, non-decreasing, in 0..G) / d_counts (device int64[ncheck]):
+// the population after each checked generation count.
 int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t* d_out,
-                hipStream_t st, const PassConfig& cfg);
+                hipStream_t st, const PassConfig& cfg, const int64_t* checks = nullptr,
+                int64_t ncheck = 0, int64_t* d_counts = nullptr);
 
 // A batch schedule bound to device buffers.
 struct DevicePlan {

@@ -172,3 +172,27 @@ def test_paired_layout_needs_a_board_below_2_gib():
     rc = gol.lib().gol_step_packed_cfg(fake, 131072, 131072, 5, fake, None, ctypes.byref(c))
     assert rc == -1
     assert b"2 GiB" in gol.lib().gol_last_error()
+
+
+@pytest.mark.parametrize("checks,G", [([3, 2], 5), ([6], 5), ([-1], 5), ([0, 5, 4], 5)])
+def test_population_checks_rejected_before_any_device_work(checks, G):
+    """Checks must be non-decreasing generation counts within 0..generations; the
+    call fails on the host, never touching the (invalid) device pointers."""
+    ch = np.asarray(checks, dtype=np.int64)
+    fake = ctypes.c_void_p(0x1000)
+    rc = gol.lib().gol_step_packed_population(fake, 64, 100, G, fake, None, None,
+                                              ch.ctypes.data, len(ch), fake)
+    assert rc == -1, gol.lib().gol_last_error()
+    assert b"checks" in gol.lib().gol_last_error()
+
+
+def test_population_null_arguments():
+    fake = ctypes.c_void_p(0x1000)
+    L = gol.lib()
+    assert L.gol_step_packed_population(fake, 64, 100, 5, fake, None, None, None, 2, fake) == -1
+    ch = np.asarray([1], dtype=np.int64)
+    assert L.gol_step_packed_population(fake, 64, 100, 5, fake, None, None, ch.ctypes.data, 1,
+                                        None) == -1
+    assert L.gol_population(None, 64, 100, fake, None) == -1
+    assert L.gol_population(fake, 64, 100, None, None) == -1
+    assert L.gol_population(fake, 0, 100, fake, None) == -1

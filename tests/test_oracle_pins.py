@@ -236,3 +236,31 @@ def test_oracle_rejects_bad_arguments():
         oracle.life(np.zeros((2, 2), np.uint8), -1)
     with pytest.raises(ValueError):
         oracle.ref.life(np.zeros((2, 2), np.uint8), -1)
+
+
+# ---------------------------------------------------------------------------
+# Population at chosen generation counts (the quantity of Table 1)
+# ---------------------------------------------------------------------------
+def test_population_at_pins():
+    """Still lifes keep their count, a blinker keeps 3, a glider keeps 5 while it
+    crosses the seams, the full 4x4 torus dies at once, and checks may repeat."""
+    pats = patterns()
+    block = place(pats["block"][3], 16, 16, 3, 4)
+    assert oracle.population_at(block, [0, 1, 50]) == [4, 4, 4]
+    blinker = place(pats["blinker"][3], 9, 11, 4, 4)
+    assert oracle.population_at(blinker, [0, 1, 2, 2, 101]) == [3, 3, 3, 3, 3]
+    glider = place(pats["glider"][3], 12, 10, 10, 8)  # crosses both seams
+    assert oracle.population_at(glider, [0, 4, 40, 120]) == [5, 5, 5, 5]
+    full = np.ones((4, 4), dtype=np.uint8)
+    assert oracle.population_at(full, [0, 1, 2]) == [16, 0, 0]
+    with pytest.raises(ValueError):
+        oracle.population_at(block, [3, 2])
+
+
+def test_population_at_matches_numpy_form():
+    """The C oracle's counts against the numpy-roll form, step by step."""
+    b = seeded_inputs.board_bytes(1209, 77, 37, 53, 0.4)
+    checks = [0, 1, 2, 5, 5, 17, 40]
+    want = [oracle.ref.population(oracle.ref.life(b, g)) for g in checks]
+    assert oracle.population_at(b, checks) == want
+    assert oracle.population_at(b, checks, threads=3) == want
