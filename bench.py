@@ -11,8 +11,9 @@ API), c3 (65536^2, 200 generations, temporal-blocked vs one generation per
 launch), c4 (4096 boards in one batched schedule vs one launch sequence per
 board), c5 (Poisson request stream through the continuous-batching server vs
 a one-at-a-time server), pop (population counting: the kernel on the 65536^2
-board and Table 1's checks on the 16384^2 run), copy (copy-kernel calibration
-of the traffic counters).
+board and Table 1's checks on the 16384^2 run), bounded (the 16384^2 board
+with dead surroundings instead of the torus), copy (copy-kernel calibration of
+the traffic counters).
 """
 from __future__ import annotations
 
@@ -493,6 +494,59 @@ def population_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def bounded_workload(args):
+    """A bounded 16384^2 board (cells beyond the edges dead), 1000 generations,
+    against the same board on the torus in the same launch configuration
+    (band layout, t_block 12 unless --t-block)."""
+    import torch
+    import paper_1209_4408_amd as gol
+    import seeded_inputs
+    R = C = 16384
+    G, p = 1000, 0.3
+    w = seeded_inputs.board_packed(SEED, 0, R, C, p)
+    d_in = torch.from_numpy(w.view(np.int64)).cuda()
+    del w
+    d_out = torch.empty_like(d_in)
+    T = args.t_block or 12
+    pd = {16: 12, 12: 9, 8: 9}.get(T, 3)
+    cfg = {"t_block": T, "band_rows": 0, "prefetch": pd, "layout": 1}
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record(st)
+        for _ in range(args.steps):
+            fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, a.elapsed_time(b) / 1e3
+    wall, dev = timed(lambda: gol.step_packed_bounded(d_in, R, C, G, d_out, config=cfg))
+    wall_t, dev_t = timed(lambda: gol.step_packed(d_in, R, C, G, d_out, config=cfg))
+    avg_launch = dev / (args.steps * G) * T
+    ops = OPS_PER_CELL_UPDATE * R * C * T
+    value = R * C * G * args.steps / wall
+    line = {"metric": "cell-updates/sec", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+            "data": "synthetic",
+            "config": {"workload": "16384x16384 bounded board (cells beyond the edges dead), "
+                                   "Bernoulli(0.3), 1000 generations", "rows": R, "cols": C,
+                       "generations": G, "p": p, "seed": SEED, **cfg, "layout": "band",
+                       "parallelism": "single GPU"},
+            "roofline": {"bound": "alu", "achieved": ops / avg_launch / 1e12,
+                         "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+                         "frac": ops / avg_launch / VALU_PEAK_OPS, "traffic": None,
+                         "kernel": f"k_board_pass<{T}, {pd}, 2>",
+                         "avg_launch_us": avg_launch * 1e6, "ops_per_launch": ops},
+            "torus_same_config": {"value": R * C * G * args.steps / wall_t,
+                                  "unit": "cell-updates/s"}}
+    print(json.dumps(line), flush=True)
+
+
 def sweep(args):
     """Single-board tuning sweep: generations per pass x band count x prefetch.
     Band counts put the wave total just under a multiple of the SIMD count."""
@@ -527,7 +581,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "copy", "pop"])
+                    choices=["c1", "c2", "c3", "c4", "c5", "copy", "pop", "bounded"])
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=2700.0,
                     help="Poisson arrival rate; requests average 1.08e10 cell-updates, so "
@@ -593,6 +647,9 @@ def main():
         return
     elif args.workload == "pop":
         population_workload(args)
+        return
+    elif args.workload == "bounded":
+        bounded_workload(args)
         return
     ms = res["wall_s"] / args.steps * 1e3
     line = {

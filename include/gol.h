@@ -115,6 +115,20 @@ int gol_step_packed_cfg(const uint64_t* d_in, int64_t rows, int64_t cols, int64_
                         uint64_t* d_out, void* stream, const gol_pass_config* config);
 
 /*
+ * Bounded board: gol_step_packed_cfg for a board whose surroundings are dead
+ * -- every cell beyond its edges is dead at every generation (such cells are
+ * not evolved), instead of the torus of Section 2.2.  Section 1 describes an
+ * infinite grid; a bounded board agrees with it as long as no cell beyond the
+ * edges would become alive.  Runs in the band layout (config->layout 0 or
+ * GOL_LAYOUT_BAND, any other -> GOL_EINVAL); t_block 0 takes the default
+ * (the autotuner's choices are for tori).  Same buffers, overlap rules and
+ * errors as gol_step_packed_cfg.
+ */
+int gol_step_packed_bounded(const uint64_t* d_in, int64_t rows, int64_t cols,
+                            int64_t generations, uint64_t* d_out, void* stream,
+                            const gol_pass_config* config);
+
+/*
  * Population: the number of live cells, the quantity the paper tabulates at
  * chosen iteration counts (Table 1).  Padding bits are not counted.
  *

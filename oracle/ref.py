@@ -45,3 +45,31 @@ def life(board: np.ndarray, generations: int) -> np.ndarray:
 def population(board: np.ndarray) -> int:
     """Live-cell count (the quantity of the paper's Table 1)."""
     return int(np.count_nonzero(board))
+
+
+def neighbour_count_bounded(board: np.ndarray) -> np.ndarray:
+    """Live-neighbour count when every cell beyond the board's edges is dead:
+    the board is surrounded by one ring of dead cells and each of the eight
+    offsets is a slice of the ringed board (no wrap)."""
+    b = (np.asarray(board) != 0).astype(np.int16)
+    R, C = b.shape[-2], b.shape[-1]
+    pad = np.zeros(b.shape[:-2] + (R + 2, C + 2), dtype=np.int16)
+    pad[..., 1:R + 1, 1:C + 1] = b
+    n = np.zeros_like(b)
+    for dr, dc in OFFSETS:
+        n += pad[..., 1 + dr:1 + dr + R, 1 + dc:1 + dc + C]
+    return n
+
+
+def life_bounded(board: np.ndarray, generations: int) -> np.ndarray:
+    """B3/S23 (Section 1 transitions, every cell at once) on a finite board in
+    a dead surrounding: cells beyond the edges are dead at every generation
+    and are not evolved."""
+    if generations < 0:
+        raise ValueError("generations must be >= 0")
+    cur = (np.asarray(board) != 0).astype(np.uint8)
+    for _ in range(generations):
+        alive = cur != 0
+        n = neighbour_count_bounded(cur)
+        cur = (((~alive) & (n == 3)) | (alive & ((n == 2) | (n == 3)))).astype(np.uint8)
+    return cur

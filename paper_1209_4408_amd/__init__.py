@@ -92,6 +92,8 @@ def lib():
             "gol_step_packed_population": (c_int, [vp, i64, i64, i64, vp, vp,
                                                    ctypes.POINTER(PassConfig), vp, i64, vp]),
             "gol_population": (c_int, [vp, i64, i64, vp, vp]),
+            "gol_step_packed_bounded": (c_int, [vp, i64, i64, i64, vp, vp,
+                                                ctypes.POINTER(PassConfig)]),
             "gol_tune_cfg": (c_int, [i64, i64, vp, ctypes.POINTER(PassConfig)]),
             "gol_pack": (c_int, [vp, i64, i64, vp, vp]),
             "gol_unpack": (c_int, [vp, i64, i64, vp, vp]),
@@ -192,6 +194,18 @@ def step_packed(d_in, rows: int, cols: int, generations: int, d_out=None, stream
     else:
         _check(lib().gol_step_packed_ex(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
                                         _stream_handle(stream), int(t_block)))
+    return d_out
+
+
+def step_packed_bounded(d_in, rows: int, cols: int, generations: int, d_out=None, stream=None,
+                        config: dict | None = None):
+    """step_packed on a bounded board: every cell beyond the edges is dead
+    (no torus).  config as for step_packed (band layout only)."""
+    if d_out is None:
+        d_out = empty_packed(rows, cols, d_in.device)
+    c = PassConfig(**{k: int(v) for k, v in (config or {}).items()})
+    _check(lib().gol_step_packed_bounded(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
+                                         _stream_handle(stream), ctypes.byref(c)))
     return d_out
 
 

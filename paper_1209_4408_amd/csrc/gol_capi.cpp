@@ -24,7 +24,7 @@ namespace gol {
 
 // Launchers defined in gol_kernels.hip.
 hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
-                             int32_t D, const GridGeom& g, int pd, hipStream_t st);
+                             int32_t D, const GridGeom& g, int pd, bool bounded, hipStream_t st);
 hipError_t launch_board_pass_half(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
                                   int32_t D, const GridGeom& g, int pd, hipStream_t st);
 hipError_t launch_population(const uint64_t* b, int64_t R, int64_t C, unsigned long long* out,
@@ -212,8 +212,10 @@ int resolve_config(int64_t R, int64_t C, const PassConfig& want, PassConfig* out
   PassConfig c = want;
   if (c.T < 0 || c.band_rows < 0 || c.pd < 0 || c.layout < 0)
     return set_error(GOL_EINVAL, "negative field in the pass configuration");
+  if (c.bounded && c.layout != 0 && c.layout != kLayoutBand)
+    return set_error(GOL_EINVAL, "a bounded board runs in the band layout (layout 0 or 1)");
   PassConfig tc;
-  if (want.T == 0 && want.layout == 0 && tuned_choice(R, C, &tc)) {
+  if (!want.bounded && want.T == 0 && want.layout == 0 && tuned_choice(R, C, &tc)) {
     c.T = tc.T;
     c.layout = tc.layout;
     if (!c.band_rows) c.band_rows = tc.band_rows;
@@ -248,7 +250,7 @@ hipError_t launch_pass(const PassConfig& c, const uint32_t* src, uint32_t* dst, 
     return launch_board_pass_half(c.T, src, dst, (int32_t)R, (int32_t)C, D,
                                   paired_geometry(R, C, c.band_rows, c.T, c.pd), c.pd, st);
   return launch_board_pass(c.T, src, dst, (int32_t)R, (int32_t)C, D,
-                           board_geometry(R, C, c.band_rows), c.pd, st);
+                           board_geometry(R, C, c.band_rows), c.pd, c.bounded, st);
 }
 
 int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t* d_out,
@@ -331,6 +333,7 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
       PassConfig r;
       r.T = o.T;
       r.layout = kLayoutBand;
+      r.bounded = c.bounded;
       r.pd = default_prefetch(r.T);
       r.band_rows = default_band_rows(R, C, r.T, simd_count());
       e = launch_pass(r, src, dst, R, C, st);
@@ -681,6 +684,26 @@ int gol_step_packed_population(const uint64_t* d_in, int64_t rows, int64_t cols,
     }
     return step_packed(d_in, rows, cols, generations, d_out, (hipStream_t)stream, cfg, checks,
                        ncheck, d_counts);
+  } catch (const std::bad_alloc&) {
+    return set_error(GOL_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(GOL_EDEVICE, "unexpected exception");
+  }
+}
+
+int gol_step_packed_bounded(const uint64_t* d_in, int64_t rows, int64_t cols,
+                            int64_t generations, uint64_t* d_out, void* stream,
+                            const gol_pass_config* config) {
+  try {
+    PassConfig cfg;
+    if (config) {
+      cfg.T = config->t_block;
+      cfg.band_rows = config->band_rows;
+      cfg.pd = config->prefetch;
+      cfg.layout = config->layout;
+    }
+    cfg.bounded = true;
+    return step_packed(d_in, rows, cols, generations, d_out, (hipStream_t)stream, cfg);
   } catch (const std::bad_alloc&) {
     return set_error(GOL_ENOMEM, "host allocation failed");
   } catch (...) {

@@ -56,6 +56,7 @@ constexpr uint32_t kE1 = (~0xF0u & (0xCCu ^ 0xAAu)) & 0xFFu;                    
 constexpr uint32_t kE2 = ((0xF0u & ~0xCCu & ~0xAAu) | (~0xF0u & 0xCCu & 0xAAu)) & 0xFFu;     // 0x18
 // sel(s, a, b) = s ? a : b
 constexpr uint32_t kSel = ((0xF0u & 0xCCu) | (~0xF0u & 0xAAu)) & 0xFFu;                    // 0xCA
+constexpr uint32_t kAnd3 = (0xF0u & 0xCCu & 0xAAu) & 0xFFu;                                 // 0x80
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, kXor3);
@@ -121,6 +122,10 @@ struct Lane {
   int32_t out_r;
   uint32_t* out_row;
   int64_t wrap;         // R * D: a row pointer that reaches row R moves back by this
+  int32_t in_u;         // input row before wrapping (bounded boards)
+  int32_t emit_base;    // r0 - T - 1: the row stage 0 emits at step i is emit_base + i
+  uint32_t vbits;       // bounded boards: bit S set if stage S emits a row of the board
+  uint32_t doff;        // bounded boards: byte offset of the lane's word, or past the row
   // store
   bool store;
   uint32_t soff;        // byte offset of the lane's dword in a row
@@ -164,6 +169,8 @@ __device__ __forceinline__ void lane_setup(Lane& L, const uint32_t* src, uint32_
   if (rin < 0) rin += R;
   L.wrap = (int64_t)R * D;
   L.in_r = (int32_t)rin;
+  L.in_u = r0 - T;
+  L.emit_base = r0 - T - 1;
   L.in_row = src + rin * (int64_t)D;
   L.out_r = r0;
   L.out_row = dst + (int64_t)r0 * D;
@@ -174,9 +181,31 @@ __device__ __forceinline__ void lane_setup(Lane& L, const uint32_t* src, uint32_
   L.hl = h;
 }
 
+// Buffer descriptor word 3 for untyped 32-bit buffer access on gfx9-family
+// parts; offsets at or past num_records are dropped by the range check.
+constexpr int kBufferDword3 = 0x00020000;
+constexpr uint32_t kDroppedOffset = 0x80000000u;
+
+// A pointer that is the same in every lane, moved to scalar registers.
+// __builtin_amdgcn_readfirstlane takes and returns 32 bits, so the two halves
+// of the 64-bit address are read separately.
+__device__ __forceinline__ uint32_t* uniform_ptr(uint32_t* p) {
+  const uint64_t v = (uint64_t)(uintptr_t)p;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (uint32_t*)(uintptr_t)(((uint64_t)hi << 32) | (uint64_t)lo);
+}
+
 struct Raw {
   uint32_t a, b;
 };
+
+// How a lane gathers its 32 columns of a row (load_raw / window):
+constexpr int kGatherTorus = 0;    // C % 32 != 0: two words of the row (Lane)
+constexpr int kGatherAligned = 1;  // C % 32 == 0: the lane's own word
+constexpr int kGatherBounded = 2;  // cells beyond the board's edges are dead:
+                                   // rows outside 0 .. R - 1 and columns outside
+                                   // 0 .. C - 1 read as 0
 
 // Boards live in global memory.  Pointers read from the batch tables are
 // generic to the compiler, and a generic (flat) load may be an LDS access that
@@ -189,17 +218,28 @@ typedef __attribute__((address_space(1))) uint32_t* GlobalOut;
 // Every lane loads every step from an address inside the board (idle lanes
 // and lanes whose gather needs one word read a valid word they ignore), so
 // the loads carry no branch and the compiler can wait for each one alone.
-template <bool ALIGNED>
+template <int GATHER>
 __device__ __forceinline__ Raw load_raw(const Lane& L) {
   Raw r;
-  r.a = ((GlobalIn)L.in_row)[L.ia];
-  r.b = ALIGNED ? 0u : ((GlobalIn)L.in_row)[L.ib];
+  if constexpr (GATHER == kGatherBounded) {
+    // a row outside the board has no records: every lane reads 0; a lane
+    // outside the row carries an offset past the row, which also reads 0
+    const bool row_in = L.in_u >= 0 && L.in_u < L.R;  // uniform
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)uniform_ptr((uint32_t*)L.in_row), 0, row_in ? L.D * 4 : 0, kBufferDword3);
+    r.a = __builtin_amdgcn_raw_buffer_load_b32(rs, L.doff, 0, 0);
+    r.b = 0u;
+  } else {
+    r.a = ((GlobalIn)L.in_row)[L.ia];
+    r.b = GATHER == kGatherAligned ? 0u : ((GlobalIn)L.in_row)[L.ib];
+  }
   return r;
 }
 
-template <bool ALIGNED>
+template <int GATHER>
 __device__ __forceinline__ uint32_t window(const Raw& r, const Lane& L) {
-  if (ALIGNED) return r.a;
+  if constexpr (GATHER == kGatherAligned) return r.a;
+  if constexpr (GATHER == kGatherBounded) return r.a & L.m1;  // the row's cells only
   if (!L.narrow)
     return __builtin_amdgcn_bitop3_b32(L.m1, __builtin_amdgcn_alignbit(r.b, r.a, L.sh),
                                        r.b << L.n1, kSel);
@@ -220,6 +260,7 @@ __device__ __forceinline__ uint32_t window(const Raw& r, const Lane& L) {
 }
 
 __device__ __forceinline__ void advance_in(Lane& L) {
+  L.in_u += 1;
   L.in_r += 1;
   L.in_row += L.D;
   if (L.in_r == L.R) {
@@ -249,7 +290,12 @@ struct Pipe {
 // rows m - 2, m - 1, m, emits generation S + 1 of row m - 1 to stage S + 1.
 // In the prologue (PRO) the step index K is known at compile time and stages
 // that have not yet received (K < 2S) or cannot yet emit (K < 2S + 2) stop.
-template <int TM, bool MASKED, int PH, int S, bool PRO, int K>
+// BND (bounded boards): every generation a stage emits keeps only cells of
+// the board -- columns outside 0 .. C - 1 (m1) and rows outside 0 .. R - 1
+// (bit S of L.vbits clear) are dead again, or a birth just beyond an edge
+// would reach the board one generation later.  The row test is a uniform
+// bit turned into a mask by arithmetic, so it costs one bitop3 and no branch.
+template <int TM, bool MASKED, int PH, int S, bool PRO, int K, bool BND = false>
 __device__ __forceinline__ void stages(uint32_t& x, Pipe<TM>& P, const Lane& L) {
   if constexpr (S < TM) {
     if constexpr (!(PRO && K < 2 * S)) {
@@ -267,8 +313,12 @@ __device__ __forceinline__ void stages(uint32_t& x, Pipe<TM>& P, const Lane& L) 
         uint32_t y = life_rule(P.lo[S][sa], P.lo[S][sc], P.lo[S][slot], P.hi[S][sa], P.hi[S][sc],
                                P.hi[S][slot], P.xs[S][sc]);
         if (MASKED) y = (S < L.Tl) ? y : P.xs[S][sc];
+        if constexpr (BND) {
+          const uint32_t rows_in = 0u - ((L.vbits >> S) & 1u);
+          y = __builtin_amdgcn_bitop3_b32(y, L.m1, rows_in, kAnd3);
+        }
         x = y;
-        stages<TM, MASKED, PH, S + 1, PRO, K>(x, P, L);
+        stages<TM, MASKED, PH, S + 1, PRO, K, BND>(x, P, L);
       }
     }
   }
@@ -277,31 +327,23 @@ __device__ __forceinline__ void stages(uint32_t& x, Pipe<TM>& P, const Lane& L) 
 // One row step.  P3 = step index mod 3 (stage slots), PP = step index mod PD
 // (the prefetch ring: the row consumed now was loaded PD steps earlier, and
 // the row PD steps ahead is requested in its place).
-// Buffer descriptor word 3 for untyped 32-bit buffer access on gfx9-family
-// parts; offsets at or past num_records are dropped by the range check.
-constexpr int kBufferDword3 = 0x00020000;
-constexpr uint32_t kDroppedOffset = 0x80000000u;
-
-// A pointer that is the same in every lane, moved to scalar registers.
-// __builtin_amdgcn_readfirstlane takes and returns 32 bits, so the two halves
-// of the 64-bit address are read separately.
-__device__ __forceinline__ uint32_t* uniform_ptr(uint32_t* p) {
-  const uint64_t v = (uint64_t)(uintptr_t)p;
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
-  return (uint32_t*)(uintptr_t)(((uint64_t)hi << 32) | (uint64_t)lo);
-}
-
-template <int TM, bool MASKED, bool ALIGNED, int PD, bool BUFST, int P3, int PP, bool PRO, int K>
+template <int TM, bool MASKED, int GATHER, int PD, bool BUFST, int P3, int PP, bool PRO, int K>
 __device__ __forceinline__ void step(int i, int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[PD]) {
-  uint32_t x = window<ALIGNED>(PF[PP], L);
+  uint32_t x = window<GATHER>(PF[PP], L);
   // rows wrap, so the PD rows requested past the band's end are valid too
-  PF[PP] = load_raw<ALIGNED>(L);
+  PF[PP] = load_raw<GATHER>(L);
   advance_in(L);
   // keep the request here, PD steps ahead of its use (the mask says which
   // instruction kinds the scheduler may still move across this point)
   __builtin_amdgcn_sched_barrier(GOL_PREFETCH_FENCE_MASK);
-  stages<TM, MASKED, P3, 0, PRO, K>(x, P, L);
+  if constexpr (GATHER == kGatherBounded) {
+    // stage S emits row emit_base + i - S (the sweep starts at row r0 - T):
+    // bit S of vbits says whether that row lies on the board
+    const int row0 = L.emit_base + i;
+    const int lo = max(0, row0 - L.R + 1), hi = min(TM - 1, row0);
+    L.vbits = lo > hi ? 0u : (((2u << hi) - 1u) & ~((1u << lo) - 1u));
+  }
+  stages<TM, MASKED, P3, 0, PRO, K, GATHER == kGatherBounded>(x, P, L);
   if constexpr (!PRO) {
     // stage TM - 1 emitted generation TM of output row i - 2 TM of the band
     if constexpr (BUFST) {
@@ -319,40 +361,40 @@ __device__ __forceinline__ void step(int i, int nsteps, Lane& L, Pipe<TM>& P, Ra
   }
 }
 
-template <int TM, bool MASKED, bool ALIGNED, int PD, bool BUFST, int K>
+template <int TM, bool MASKED, int GATHER, int PD, bool BUFST, int K>
 __device__ __forceinline__ void prologue(int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[PD]) {
   if constexpr (K < 2 * TM) {
-    step<TM, MASKED, ALIGNED, PD, BUFST, K % 3, K % PD, true, K>(K, nsteps, L, P, PF);
-    prologue<TM, MASKED, ALIGNED, PD, BUFST, K + 1>(nsteps, L, P, PF);
+    step<TM, MASKED, GATHER, PD, BUFST, K % 3, K % PD, true, K>(K, nsteps, L, P, PF);
+    prologue<TM, MASKED, GATHER, PD, BUFST, K + 1>(nsteps, L, P, PF);
   }
 }
 
 // Steady state: PD consecutive steps starting at a step index congruent to
 // 2 TM modulo PD (PD is 3 or 6, so the slot phase is fixed too).
-template <int TM, bool MASKED, bool ALIGNED, int PD, bool BUFST, int U>
+template <int TM, bool MASKED, int GATHER, int PD, bool BUFST, int U>
 __device__ __forceinline__ void body(int i, int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[PD]) {
   if constexpr (U < PD) {
     constexpr int k = 2 * TM + U;
-    step<TM, MASKED, ALIGNED, PD, BUFST, k % 3, k % PD, false, 0>(i + U, nsteps, L, P, PF);
-    body<TM, MASKED, ALIGNED, PD, BUFST, U + 1>(i, nsteps, L, P, PF);
+    step<TM, MASKED, GATHER, PD, BUFST, k % 3, k % PD, false, 0>(i + U, nsteps, L, P, PF);
+    body<TM, MASKED, GATHER, PD, BUFST, U + 1>(i, nsteps, L, P, PF);
   }
 }
 
-template <int TM, bool MASKED, bool ALIGNED, int PD, bool BUFST, int U>
+template <int TM, bool MASKED, int GATHER, int PD, bool BUFST, int U>
 __device__ __forceinline__ void tail(int i, int nsteps, Lane& L, Pipe<TM>& P, Raw (&PF)[PD]) {
   if constexpr (U < PD - 1) {
     if (i + U < nsteps) {
       constexpr int k = 2 * TM + U;
-      step<TM, MASKED, ALIGNED, PD, BUFST, k % 3, k % PD, false, 0>(i + U, nsteps, L, P, PF);
-      tail<TM, MASKED, ALIGNED, PD, BUFST, U + 1>(i, nsteps, L, P, PF);
+      step<TM, MASKED, GATHER, PD, BUFST, k % 3, k % PD, false, 0>(i + U, nsteps, L, P, PF);
+      tail<TM, MASKED, GATHER, PD, BUFST, U + 1>(i, nsteps, L, P, PF);
     }
   }
 }
 
 // Sweep one tile: H output rows (the wave's largest band), TM generations,
 // input rows requested PD steps ahead of use.
-template <int TM, bool MASKED, bool ALIGNED, int PD, bool BUFST>
-__device__ void run_tile(Lane& L, int H) {
+template <int TM, bool MASKED, int GATHER, int PD, bool BUFST>
+__device__ __forceinline__ void run_tile(Lane& L, int H) {
   static_assert(TM >= 1 && TM <= kMaxT, "generations per pass");
   static_assert(PD % 3 == 0 && PD >= 3, "prefetch distance");
   Pipe<TM> P;
@@ -360,13 +402,13 @@ __device__ void run_tile(Lane& L, int H) {
   const int nsteps = H + 2 * TM;  // >= 3
 #pragma unroll
   for (int k = 0; k < PD; ++k) {
-    PF[k] = load_raw<ALIGNED>(L);
+    PF[k] = load_raw<GATHER>(L);
     advance_in(L);
   }
-  prologue<TM, MASKED, ALIGNED, PD, BUFST, 0>(nsteps, L, P, PF);
+  prologue<TM, MASKED, GATHER, PD, BUFST, 0>(nsteps, L, P, PF);
   int i = 2 * TM;
-  for (; i + PD - 1 < nsteps; i += PD) body<TM, MASKED, ALIGNED, PD, BUFST, 0>(i, nsteps, L, P, PF);
-  tail<TM, MASKED, ALIGNED, PD, BUFST, 0>(i, nsteps, L, P, PF);
+  for (; i + PD - 1 < nsteps; i += PD) body<TM, MASKED, GATHER, PD, BUFST, 0>(i, nsteps, L, P, PF);
+  tail<TM, MASKED, GATHER, PD, BUFST, 0>(i, nsteps, L, P, PF);
 }
 
 // Workgroups are dealt to the 8 XCDs of the chip in turn; give each XCD a
@@ -386,7 +428,7 @@ struct PassArgs {
   int32_t R, C, D;
 };
 
-template <int TM, int PD, bool ALIGNED>
+template <int TM, int PD, int GATHER>
 __global__ __launch_bounds__(64) void k_board_pass(PassArgs a, GridGeom g) {
   const int nitems = g.nstrips * g.nbands;
   const int item = xcd_item(nitems);
@@ -401,7 +443,23 @@ __global__ __launch_bounds__(64) void k_board_pass(PassArgs a, GridGeom g) {
   Lane L;
   lane_setup(L, a.src, a.dst, a.R, a.C, a.D, ds - 1 + lane, lane, nl, rb, hb, TM, TM, lane < nl);
   if (!L.store) L.soff = kDroppedOffset;
-  run_tile<TM, false, ALIGNED, PD, true>(L, hb);
+  if constexpr (GATHER == kGatherBounded) {
+    const int p = ds - 1 + lane;
+    const int nd = (a.C + 31) >> 5;
+    // A tile whose sweep reads only rows rb - T .. rb + hb + T - 1 and whole
+    // dwords ds - 1 .. ds + us of the board never meets an edge: the plain
+    // gather of the lane's own dword (ia == p there) serves it, with no masks.
+    if (rb - TM >= 0 && rb + hb + TM <= a.R && ds >= 1 && ds + us < (a.C >> 5)) {
+      run_tile<TM, false, kGatherAligned, PD, true>(L, hb);
+      return;
+    }
+    const bool col_in = p >= 0 && p < nd;
+    const int64_t c0 = (int64_t)p * 32;
+    L.doff = col_in ? (uint32_t)p * 4u : kDroppedOffset;
+    L.m1 = !col_in ? 0u
+                   : (c0 + 32 <= a.C ? 0xFFFFFFFFu : ((1u << (uint32_t)(a.C - c0)) - 1u));
+  }
+  run_tile<TM, false, GATHER, PD, true>(L, hb);
 }
 
 // ---------------------------------------------------------------------------
@@ -580,7 +638,7 @@ __device__ __forceinline__ void hepilogue(uint32_t xin, HalfLane& L, Pipe<TM>& P
 
 // One wave's sweep: H + 2 TM steps, the last TM of them the epilogue.
 template <int TM, int PD, bool WRAP>
-__device__ void run_tile_half(HalfLane& L, int H, __amdgpu_buffer_rsrc_t rsrc,
+__device__ __forceinline__ void run_tile_half(HalfLane& L, int H, __amdgpu_buffer_rsrc_t rsrc,
                               __amdgpu_buffer_rsrc_t rdst) {
   Pipe<TM> P;
   uint32_t PF[PD];
@@ -686,9 +744,9 @@ __global__ __launch_bounds__(64) void k_batch_pass(const BoardDesc* __restrict__
     lane_setup(L, bd.src0, bd.w[0], bd.R, bd.C, bd.D, 0, 0, 1, 0, 1, TM, TM, false);
   }
   if (w.flags & kItemAligned)
-    run_tile<TM, MASKED, true, GOL_BATCH_PREFETCH, false>(L, w.h);
+    run_tile<TM, MASKED, kGatherAligned, GOL_BATCH_PREFETCH, false>(L, w.h);
   else
-    run_tile<TM, MASKED, false, GOL_BATCH_PREFETCH, false>(L, w.h);
+    run_tile<TM, MASKED, kGatherTorus, GOL_BATCH_PREFETCH, false>(L, w.h);
 }
 
 // ---------------------------------------------------------------------------
@@ -797,22 +855,26 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
 // Host-side launchers (called by the C ABI in gol_capi.cpp).
 // ---------------------------------------------------------------------------
 template <int TM, int PD>
-static hipError_t launch_board_pass_t(const PassArgs& a, const GridGeom& g, hipStream_t st) {
+static hipError_t launch_board_pass_t(const PassArgs& a, const GridGeom& g, bool bounded,
+                                      hipStream_t st) {
   const int nitems = g.nstrips * g.nbands;
   const int grid = ((nitems + 7) / 8) * 8;
-  if ((a.C & 31) == 0)
-    hipLaunchKernelGGL((k_board_pass<TM, PD, true>), dim3(grid), dim3(64), 0, st, a, g);
+  if (bounded)
+    hipLaunchKernelGGL((k_board_pass<TM, PD, kGatherBounded>), dim3(grid), dim3(64), 0, st, a, g);
+  else if ((a.C & 31) == 0)
+    hipLaunchKernelGGL((k_board_pass<TM, PD, kGatherAligned>), dim3(grid), dim3(64), 0, st, a, g);
   else
-    hipLaunchKernelGGL((k_board_pass<TM, PD, false>), dim3(grid), dim3(64), 0, st, a, g);
+    hipLaunchKernelGGL((k_board_pass<TM, PD, kGatherTorus>), dim3(grid), dim3(64), 0, st, a, g);
   return hipGetLastError();
 }
 
 // One band per wave; (T, pd) must satisfy pass_config_compiled(kLayoutBand, ...).
+// bounded: cells beyond the board's edges are dead (no torus).
 hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
-                             int32_t D, const GridGeom& g, int pd, hipStream_t st) {
+                             int32_t D, const GridGeom& g, int pd, bool bounded, hipStream_t st) {
   PassArgs a{src, dst, R, C, D};
 #define GOL_LAUNCH_BAND(TV, PDV) \
-  if (T == TV && pd == PDV) return launch_board_pass_t<TV, PDV>(a, g, st);
+  if (T == TV && pd == PDV) return launch_board_pass_t<TV, PDV>(a, g, bounded, st);
   GOL_LAUNCH_BAND(1, 3)
   GOL_LAUNCH_BAND(1, 6)
   GOL_LAUNCH_BAND(2, 3)

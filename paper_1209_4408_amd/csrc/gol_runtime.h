@@ -36,6 +36,7 @@ struct PassConfig {
   int band_rows = 0;
   int pd = 0;
   int layout = 0;
+  bool bounded = false;  // cells beyond the edges are dead (no torus); band layout only
 };
 // The autotuner's choice for a board size on the current device, if any.
 bool tuned_choice(int64_t rows, int64_t cols, PassConfig* out);

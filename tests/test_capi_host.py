@@ -196,3 +196,11 @@ def test_population_null_arguments():
     assert L.gol_population(None, 64, 100, fake, None) == -1
     assert L.gol_population(fake, 64, 100, None, None) == -1
     assert L.gol_population(fake, 0, 100, fake, None) == -1
+
+
+def test_bounded_board_rejects_the_paired_layout():
+    c = gol.PassConfig(12, 0, 9, 2)
+    fake = ctypes.c_void_p(0x1000)
+    rc = gol.lib().gol_step_packed_bounded(fake, 64, 128, 5, fake, None, ctypes.byref(c))
+    assert rc == -1
+    assert b"band layout" in gol.lib().gol_last_error()

@@ -264,3 +264,72 @@ def test_population_at_matches_numpy_form():
     want = [oracle.ref.population(oracle.ref.life(b, g)) for g in checks]
     assert oracle.population_at(b, checks) == want
     assert oracle.population_at(b, checks, threads=3) == want
+
+
+# ---------------------------------------------------------------------------
+# Bounded boards (cells beyond the edges dead at every generation)
+# ---------------------------------------------------------------------------
+def bounded_brute(board, generations):
+    """Cell by cell: count the in-board neighbours with explicit loops."""
+    cur = [[int(v != 0) for v in row] for row in board]
+    R, C = len(cur), len(cur[0])
+    for _ in range(generations):
+        nxt = [[0] * C for _ in range(R)]
+        for r in range(R):
+            for c in range(C):
+                n = 0
+                for dr in (-1, 0, 1):
+                    for dc in (-1, 0, 1):
+                        if (dr or dc) and 0 <= r + dr < R and 0 <= c + dc < C:
+                            n += cur[r + dr][c + dc]
+                nxt[r][c] = 1 if n == 3 or (cur[r][c] and n == 2) else 0
+        cur = nxt
+    return np.array(cur, dtype=np.uint8)
+
+
+@pytest.mark.parametrize("R,C", [(1, 1), (1, 7), (2, 2), (3, 3), (4, 9), (7, 5), (9, 12)])
+def test_bounded_brute_force(R, C):
+    for k in range(6):
+        b = seeded_inputs.board_bytes(555, 10 * R + C + k, R, C, 0.45)
+        for g in (0, 1, 2, 5):
+            assert np.array_equal(oracle.ref.life_bounded(b, g), bounded_brute(b, g)), (R, C, k, g)
+
+
+@pytest.mark.parametrize("R,C", [(3, 3), (4, 7), (10, 6), (16, 16)])
+def test_bounded_full_board(R, C):
+    """Closed form: a full board keeps only its four corners (3 neighbours each;
+    edge cells have 5, inner cells 8), which then die alone."""
+    full = np.ones((R, C), dtype=np.uint8)
+    g1 = oracle.ref.life_bounded(full, 1)
+    corners = np.zeros((R, C), dtype=np.uint8)
+    corners[0, 0] = corners[0, -1] = corners[-1, 0] = corners[-1, -1] = 1
+    assert np.array_equal(g1, corners)
+    assert not oracle.ref.life_bounded(full, 2).any()
+    # 2 x 2: every cell has three neighbours, a block
+    assert oracle.ref.life_bounded(np.ones((2, 2), dtype=np.uint8), 5).all()
+
+
+@pytest.mark.parametrize("C", [1, 2, 5, 12])
+def test_bounded_line_shrinks(C):
+    """A full 1 x C line loses its two end cells every generation."""
+    line = np.ones((1, C), dtype=np.uint8)
+    for g in range(0, C + 2):
+        want = np.zeros((1, C), dtype=np.uint8)
+        want[0, g:C - g] = 1
+        assert np.array_equal(oracle.ref.life_bounded(line, g), want), (C, g)
+
+
+def test_bounded_equals_torus_away_from_the_edges():
+    """Live cells kept more than G cells from every edge never meet the
+    boundary within G generations, so both boundaries give the same board."""
+    inner = seeded_inputs.board_bytes(556, 0, 20, 30, 0.4)
+    b = np.zeros((20 + 2 * 13, 30 + 2 * 13), dtype=np.uint8)
+    b[13:33, 13:43] = inner
+    for g in (1, 6, 12):
+        assert np.array_equal(oracle.ref.life_bounded(b, g), oracle.life(b, g))
+
+
+def test_bounded_block_in_a_corner():
+    b = np.zeros((6, 6), dtype=np.uint8)
+    b[:2, :2] = 1
+    assert np.array_equal(oracle.ref.life_bounded(b, 9), b)
