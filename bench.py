@@ -12,7 +12,8 @@ launch), c4 (4096 boards in one batched schedule vs one launch sequence per
 board), c5 (Poisson request stream through the continuous-batching server vs
 a one-at-a-time server), pop (population counting: the kernel on the 65536^2
 board and Table 1's checks on the 16384^2 run), bounded (the 16384^2 board
-with dead surroundings instead of the torus), copy (copy-kernel calibration of
+with dead surroundings instead of the torus), strip (one GPU's 8192 x 65536
+share of the 65536^2 board, halo rows from separate buffers), copy (copy-kernel calibration of
 the traffic counters).
 """
 from __future__ import annotations
@@ -547,6 +548,87 @@ def bounded_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def strip_workload(args):
+    """One GPU's share of the 65536^2 board under the row decomposition over 8
+    GPUs: an 8192 x 65536 strip, 200 generations in passes of t (16 unless
+    --t-block; a shorter last pass), each pass reading its halo rows from two
+    separate buffers.  Before each pass the halo buffers are refilled by device
+    copies from the strip's own edge rows -- the one-GPU ring, where the strip
+    is a whole 8192 x 65536 torus; across GPUs the neighbours would send them.
+    Against the whole 65536^2 board in the same configuration."""
+    import torch
+    import paper_1209_4408_amd as gol
+    import seeded_inputs
+    rows, C, G, p = 8192, 65536, 200, 0.5
+    t = args.t_block or 16
+    pd = {16: 12, 12: 9, 8: 9}.get(t, 3)  # the library's default prefetch for t
+    passes = [t] * (G // t) + ([G % t] if G % t else [])
+    if any(x not in (1, 2, 4, 8, 12, 16) for x in passes):
+        raise SystemExit(f"200 generations in passes of {t} leave a pass length with no kernel")
+    w = seeded_inputs.board_packed(SEED, 8, rows, C, p)
+    cur = torch.from_numpy(w.view(np.int64)).cuda()
+    del w
+    nxt = torch.empty_like(cur)
+    W = cur.shape[1]
+    top = torch.empty((max(passes), W), dtype=torch.int64, device="cuda")
+    bot = torch.empty_like(top)
+    st = torch.cuda.current_stream()
+
+    def run():
+        nonlocal cur, nxt
+        for x in passes:
+            top[:x].copy_(cur[rows - x:])
+            bot[:x].copy_(cur[:x])
+            gol.strip_pass(cur, top, bot, rows, C, x, d_out=nxt)
+            cur, nxt = nxt, cur
+
+    def kernels_only():
+        for x in passes:
+            gol.strip_pass(cur, top, bot, rows, C, x, d_out=nxt)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record(st)
+        for _ in range(args.steps):
+            fn()
+        b.record(st)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, a.elapsed_time(b) / 1e3
+    wall, _ = timed(run)
+    _, dev_k = timed(kernels_only)
+    # the whole board for comparison: the 65536^2 run of the same generations
+    R2 = 65536
+    big = torch.from_numpy(seeded_inputs.board_packed(SEED, 0, R2, C, p).view(np.int64)).cuda()
+    big_out = torch.empty_like(big)
+    cfg = {"t_block": t, "layout": 1}
+    wall_big, _ = timed(lambda: gol.step_packed(big, R2, C, G, big_out, config=cfg))
+    del big, big_out
+    avg_launch = dev_k / (args.steps * len(passes))
+    ops = OPS_PER_CELL_UPDATE * rows * C * G / len(passes)  # average per launch
+    value = rows * C * G * args.steps / wall
+    line = {"metric": "cell-updates/sec", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+            "data": "synthetic",
+            "config": {"workload": "8192x65536 strip of a 65536^2 torus (one of 8 row strips), "
+                                   "halo rows from separate buffers, Bernoulli(0.5), "
+                                   "200 generations", "rows": rows, "cols": C, "generations": G,
+                       "p": p, "seed": SEED, "passes": passes, "layout": "band",
+                       "parallelism": "single GPU (one GPU's share)"},
+            "roofline": {"bound": "alu", "achieved": ops / avg_launch / 1e12,
+                         "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+                         "frac": ops / avg_launch / VALU_PEAK_OPS, "traffic": None,
+                         "kernel": f"k_board_pass<{t}, {pd}, 5>",
+                         "avg_launch_us": avg_launch * 1e6, "ops_per_launch": ops},
+            "whole_board_same_t": {"value": R2 * C * G * args.steps / wall_big,
+                                   "unit": "cell-updates/s"}}
+    print(json.dumps(line), flush=True)
+
+
 def sweep(args):
     """Single-board tuning sweep: generations per pass x band count x prefetch.
     Band counts put the wave total just under a multiple of the SIMD count."""
@@ -581,7 +663,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "copy", "pop", "bounded"])
+                    choices=["c1", "c2", "c3", "c4", "c5", "copy", "pop", "bounded",
+                             "strip"])
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=2700.0,
                     help="Poisson arrival rate; requests average 1.08e10 cell-updates, so "
@@ -650,6 +733,9 @@ def main():
         return
     elif args.workload == "bounded":
         bounded_workload(args)
+        return
+    elif args.workload == "strip":
+        strip_workload(args)
         return
     ms = res["wall_s"] / args.steps * 1e3
     line = {

@@ -129,6 +129,31 @@ int gol_step_packed_bounded(const uint64_t* d_in, int64_t rows, int64_t cols,
                             const gol_pass_config* config);
 
 /*
+ * Strip pass: t generations of one row strip of a larger torus, whose
+ * neighbouring rows are held elsewhere -- the unit of the row (1-D)
+ * decomposition of Section 2.1 (Figure 1), where each worker updates a bar of
+ * whole rows; the rows just beyond its edges belong to its neighbours (the
+ * boundary reads Section 2.2 describes for sub-regions).  Across devices the
+ * strips would form a ring and trade t edge rows per pass.
+ *   d_strip  : rows x W words (W = ceil(cols / 64)), the strip at generation g.
+ *   d_top    : t x W words, the t rows just above the strip's first row,
+ *              farthest first (its last row touches the strip).
+ *   d_bottom : t x W words, the t rows just below the strip's last row,
+ *              nearest first.
+ *   d_out    : rows x W words, receives the strip at generation g + t.
+ * Each row is a whole torus row: columns wrap within the row.  t must be 1, 2,
+ * 4, 8, 12 or 16 (one pass; the halo rows are only known at generation g).
+ * config (may be NULL): band_rows and prefetch as for gol_step_packed_cfg;
+ * t_block must be 0 or t and layout 0 or GOL_LAYOUT_BAND.  Padding bits of the
+ * inputs are ignored and written as 0.  d_out must not overlap any input
+ * (GOL_EINVAL); null buffers, sizes outside [1, 2^30] -> GOL_EINVAL.
+ * Asynchronous on stream; the inputs must stay valid until it completes.
+ */
+int gol_strip_pass(const uint64_t* d_strip, const uint64_t* d_top, const uint64_t* d_bottom,
+                   int64_t rows, int64_t cols, int64_t t, uint64_t* d_out, void* stream,
+                   const gol_pass_config* config);
+
+/*
  * Population: the number of live cells, the quantity the paper tabulates at
  * chosen iteration counts (Table 1).  Padding bits are not counted.
  *

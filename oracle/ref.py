@@ -73,3 +73,38 @@ def life_bounded(board: np.ndarray, generations: int) -> np.ndarray:
         n = neighbour_count_bounded(cur)
         cur = (((~alive) & (n == 3)) | (alive & ((n == 2) | (n == 3)))).astype(np.uint8)
     return cur
+
+
+def strip_pass(strip: np.ndarray, top: np.ndarray, bottom: np.ndarray,
+               generations: int) -> np.ndarray:
+    """A row strip of a larger torus after ``generations`` (= t) generations,
+    given the t rows above it (``top``, farthest first) and the t rows below
+    it (``bottom``, nearest first) at the start: the unit of the row
+    decomposition of Section 2.1.  Rows are whole torus rows, so columns wrap.
+
+    A cell's state after t generations depends only on cells within t rows of
+    it (one row per generation), so the strip's rows follow from the stacked
+    rows top | strip | bottom alone.  The stack is evolved with nothing above
+    or below it (those rows read as dead) and columns wrapping; whatever that
+    cut changes spreads inwards one row per generation and stays inside the
+    t halo rows, which are dropped."""
+    t = int(generations)
+    if t < 0:
+        raise ValueError("generations must be >= 0")
+    s = (np.asarray(strip) != 0).astype(np.uint8)
+    a = (np.asarray(top) != 0).astype(np.uint8)
+    b = (np.asarray(bottom) != 0).astype(np.uint8)
+    if a.shape != (t, s.shape[1]) or b.shape != (t, s.shape[1]):
+        raise ValueError("top and bottom must hold t rows of the strip's width")
+    cur = np.concatenate([a, s, b], axis=0)
+    H, C = cur.shape
+    for _ in range(t):
+        pad = np.zeros((H + 2, C), dtype=np.int16)
+        pad[1:H + 1] = cur
+        n = np.zeros((H, C), dtype=np.int16)
+        for dr, dc in OFFSETS:
+            # rows: no wrap (slice of the padded stack); columns: wrap (roll)
+            n += np.roll(pad[1 + dr:1 + dr + H], shift=-dc, axis=1)
+        alive = cur != 0
+        cur = (((~alive) & (n == 3)) | (alive & ((n == 2) | (n == 3)))).astype(np.uint8)
+    return cur[t:t + s.shape[0]]

@@ -94,6 +94,8 @@ def lib():
             "gol_population": (c_int, [vp, i64, i64, vp, vp]),
             "gol_step_packed_bounded": (c_int, [vp, i64, i64, i64, vp, vp,
                                                 ctypes.POINTER(PassConfig)]),
+            "gol_strip_pass": (c_int, [vp, vp, vp, i64, i64, i64, vp, vp,
+                                       ctypes.POINTER(PassConfig)]),
             "gol_tune_cfg": (c_int, [i64, i64, vp, ctypes.POINTER(PassConfig)]),
             "gol_pack": (c_int, [vp, i64, i64, vp, vp]),
             "gol_unpack": (c_int, [vp, i64, i64, vp, vp]),
@@ -206,6 +208,19 @@ def step_packed_bounded(d_in, rows: int, cols: int, generations: int, d_out=None
     c = PassConfig(**{k: int(v) for k, v in (config or {}).items()})
     _check(lib().gol_step_packed_bounded(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
                                          _stream_handle(stream), ctypes.byref(c)))
+    return d_out
+
+
+def strip_pass(d_strip, d_top, d_bottom, rows: int, cols: int, t: int, d_out=None, stream=None,
+               config: dict | None = None):
+    """t generations of a row strip of a larger torus: d_top holds the t rows
+    above the strip (farthest first), d_bottom the t rows below it (nearest
+    first); columns wrap.  Returns d_out (the strip at generation + t)."""
+    if d_out is None:
+        d_out = empty_packed(rows, cols, d_strip.device)
+    c = PassConfig(**{k: int(v) for k, v in (config or {}).items()})
+    _check(lib().gol_strip_pass(_ptr(d_strip), _ptr(d_top), _ptr(d_bottom), rows, cols, int(t),
+                                _ptr(d_out), _stream_handle(stream), ctypes.byref(c)))
     return d_out
 
 

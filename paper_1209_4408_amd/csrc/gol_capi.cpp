@@ -24,7 +24,8 @@ namespace gol {
 
 // Launchers defined in gol_kernels.hip.
 hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
-                             int32_t D, const GridGeom& g, int pd, bool bounded, hipStream_t st);
+                             int32_t D, const GridGeom& g, int pd, bool bounded, hipStream_t st,
+                             const uint32_t* top = nullptr, const uint32_t* bot = nullptr);
 hipError_t launch_board_pass_half(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
                                   int32_t D, const GridGeom& g, int pd, hipStream_t st);
 hipError_t launch_population(const uint64_t* b, int64_t R, int64_t C, unsigned long long* out,
@@ -170,6 +171,11 @@ bool ranges_partially_overlap(const void* a, const void* b, size_t bytes) {
   const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
   if (x == y) return false;
   return x < y + bytes && y < x + bytes;
+}
+
+static bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + bbytes && y < x + abytes;
 }
 
 int default_T() { return 12; }
@@ -709,6 +715,50 @@ int gol_step_packed_bounded(const uint64_t* d_in, int64_t rows, int64_t cols,
   } catch (...) {
     return set_error(GOL_EDEVICE, "unexpected exception");
   }
+}
+
+int gol_strip_pass(const uint64_t* d_strip, const uint64_t* d_top, const uint64_t* d_bottom,
+                   int64_t rows, int64_t cols, int64_t t, uint64_t* d_out, void* stream,
+                   const gol_pass_config* config) {
+  int rc = check_board(rows, cols, t);
+  if (rc) return rc;
+  if (!d_strip || !d_top || !d_bottom || !d_out)
+    return set_error(GOL_EINVAL, "null buffer");
+  if (t < 1 || t > 16 || !valid_board_T((int)t))
+    return set_error(GOL_EINVAL, "t must be 1, 2, 4, 8, 12 or 16 (got %lld)", (long long)t);
+  const int T = (int)t;
+  PassConfig c;
+  if (config) {
+    if (config->t_block != 0 && config->t_block != T)
+      return set_error(GOL_EINVAL, "config t_block must be 0 or t");
+    if (config->layout != 0 && config->layout != kLayoutBand)
+      return set_error(GOL_EINVAL, "a strip runs in the band layout (layout 0 or 1)");
+    if (config->band_rows < 0 || config->prefetch < 0)
+      return set_error(GOL_EINVAL, "negative field in the pass configuration");
+    c.band_rows = config->band_rows;
+    c.pd = config->prefetch;
+  }
+  const int64_t W = (cols + 63) / 64;
+  const size_t sb = (size_t)(rows * W * 8), hb = (size_t)(t * W * 8);
+  if (ranges_overlap(d_out, sb, d_strip, sb) || ranges_overlap(d_out, sb, d_top, hb) ||
+      ranges_overlap(d_out, sb, d_bottom, hb))
+    return set_error(GOL_EINVAL, "d_out overlaps an input");
+  PassConfig tc;
+  if (!c.band_rows && !c.pd && tuned_choice(rows, cols, &tc) && tc.layout == kLayoutBand &&
+      tc.T == T) {
+    c.band_rows = tc.band_rows;
+    c.pd = tc.pd;
+  }
+  if (!c.pd) c.pd = default_prefetch(T);
+  if (!pass_config_compiled(kLayoutBand, T, c.pd))
+    return set_error(GOL_EINVAL, "prefetch %d is not built for the band layout with t %d", c.pd, T);
+  if (!c.band_rows) c.band_rows = default_band_rows(rows, cols, T, simd_count());
+  const int32_t D = (int32_t)(2 * W);
+  const hipError_t e = launch_board_pass(
+      T, (const uint32_t*)d_strip, (uint32_t*)d_out, (int32_t)rows, (int32_t)cols, D,
+      board_geometry(rows, cols, c.band_rows), c.pd, false, (hipStream_t)stream,
+      (const uint32_t*)d_top, (const uint32_t*)d_bottom);
+  return e == hipSuccess ? GOL_OK : hip_error(e, "strip pass launch");
 }
 
 int gol_population(const uint64_t* d_packed, int64_t rows, int64_t cols, int64_t* d_count,

@@ -122,7 +122,9 @@ struct Lane {
   int32_t out_r;
   uint32_t* out_row;
   int64_t wrap;         // R * D: a row pointer that reaches row R moves back by this
-  int32_t in_u;         // input row before wrapping (bounded boards)
+  int32_t in_u;         // input row before wrapping (bounded boards, strips)
+  const uint32_t* mid;  // strips: the strip's row 0
+  const uint32_t* bot;  // strips: the first row below the strip
   int32_t emit_base;    // r0 - T - 1: the row stage 0 emits at step i is emit_base + i
   uint32_t vbits;       // bounded boards: bit S set if stage S emits a row of the board
   uint32_t doff;        // bounded boards: byte offset of the lane's word, or past the row
@@ -206,6 +208,11 @@ constexpr int kGatherAligned = 1;  // C % 32 == 0: the lane's own word
 constexpr int kGatherBounded = 2;  // cells beyond the board's edges are dead:
                                    // rows outside 0 .. R - 1 and columns outside
                                    // 0 .. C - 1 read as 0
+// Added to kGatherTorus or kGatherAligned: the R rows are a strip of a larger
+// torus; the rows above and below it come from two other buffers (halo rows)
+// instead of wrapping around the strip.  Columns still wrap.
+constexpr int kHaloRows = 4;
+constexpr int col_gather(int g) { return g & 3; }
 
 // Boards live in global memory.  Pointers read from the batch tables are
 // generic to the compiler, and a generic (flat) load may be an LDS access that
@@ -231,14 +238,14 @@ __device__ __forceinline__ Raw load_raw(const Lane& L) {
     r.b = 0u;
   } else {
     r.a = ((GlobalIn)L.in_row)[L.ia];
-    r.b = GATHER == kGatherAligned ? 0u : ((GlobalIn)L.in_row)[L.ib];
+    r.b = col_gather(GATHER) == kGatherAligned ? 0u : ((GlobalIn)L.in_row)[L.ib];
   }
   return r;
 }
 
 template <int GATHER>
 __device__ __forceinline__ uint32_t window(const Raw& r, const Lane& L) {
-  if constexpr (GATHER == kGatherAligned) return r.a;
+  if constexpr (col_gather(GATHER) == kGatherAligned) return r.a;
   if constexpr (GATHER == kGatherBounded) return r.a & L.m1;  // the row's cells only
   if (!L.narrow)
     return __builtin_amdgcn_bitop3_b32(L.m1, __builtin_amdgcn_alignbit(r.b, r.a, L.sh),
@@ -259,8 +266,21 @@ __device__ __forceinline__ uint32_t window(const Raw& r, const Lane& L) {
   return (uint32_t)(v >> L.sh);
 }
 
+template <int GATHER>
 __device__ __forceinline__ void advance_in(Lane& L) {
   L.in_u += 1;
+  if constexpr ((GATHER & kHaloRows) != 0) {
+    // rows -T .. -1 from the top halo, 0 .. R - 1 from the strip, R .. R + T - 1
+    // from the bottom halo; the prefetch past the tile's last row (never used)
+    // re-reads the bottom halo's last row
+    if (L.in_u == 0)
+      L.in_row = L.mid;
+    else if (L.in_u == L.R)
+      L.in_row = L.bot;
+    else if (L.in_u < L.R + L.Tl)
+      L.in_row += L.D;
+    return;
+  }
   L.in_r += 1;
   L.in_row += L.D;
   if (L.in_r == L.R) {
@@ -332,7 +352,7 @@ __device__ __forceinline__ void step(int i, int nsteps, Lane& L, Pipe<TM>& P, Ra
   uint32_t x = window<GATHER>(PF[PP], L);
   // rows wrap, so the PD rows requested past the band's end are valid too
   PF[PP] = load_raw<GATHER>(L);
-  advance_in(L);
+  advance_in<GATHER>(L);
   // keep the request here, PD steps ahead of its use (the mask says which
   // instruction kinds the scheduler may still move across this point)
   __builtin_amdgcn_sched_barrier(GOL_PREFETCH_FENCE_MASK);
@@ -403,7 +423,7 @@ __device__ __forceinline__ void run_tile(Lane& L, int H) {
 #pragma unroll
   for (int k = 0; k < PD; ++k) {
     PF[k] = load_raw<GATHER>(L);
-    advance_in(L);
+    advance_in<GATHER>(L);
   }
   prologue<TM, MASKED, GATHER, PD, BUFST, 0>(nsteps, L, P, PF);
   int i = 2 * TM;
@@ -426,6 +446,8 @@ struct PassArgs {
   const uint32_t* src;
   uint32_t* dst;
   int32_t R, C, D;
+  const uint32_t* top;  // strips (kHaloRows): T rows above row 0, the farthest first
+  const uint32_t* bot;  // strips: T rows below row R - 1, the nearest first
 };
 
 template <int TM, int PD, int GATHER>
@@ -443,6 +465,11 @@ __global__ __launch_bounds__(64) void k_board_pass(PassArgs a, GridGeom g) {
   Lane L;
   lane_setup(L, a.src, a.dst, a.R, a.C, a.D, ds - 1 + lane, lane, nl, rb, hb, TM, TM, lane < nl);
   if (!L.store) L.soff = kDroppedOffset;
+  if constexpr ((GATHER & kHaloRows) != 0) {
+    L.mid = a.src;
+    L.bot = a.bot;
+    L.in_row = L.in_u < 0 ? a.top + (int64_t)(L.in_u + TM) * a.D : a.src + (int64_t)L.in_u * a.D;
+  }
   if constexpr (GATHER == kGatherBounded) {
     const int p = ds - 1 + lane;
     const int nd = (a.C + 31) >> 5;
@@ -859,7 +886,13 @@ static hipError_t launch_board_pass_t(const PassArgs& a, const GridGeom& g, bool
                                       hipStream_t st) {
   const int nitems = g.nstrips * g.nbands;
   const int grid = ((nitems + 7) / 8) * 8;
-  if (bounded)
+  if (a.top && (a.C & 31) == 0)
+    hipLaunchKernelGGL((k_board_pass<TM, PD, kGatherAligned | kHaloRows>), dim3(grid), dim3(64), 0,
+                       st, a, g);
+  else if (a.top)
+    hipLaunchKernelGGL((k_board_pass<TM, PD, kGatherTorus | kHaloRows>), dim3(grid), dim3(64), 0,
+                       st, a, g);
+  else if (bounded)
     hipLaunchKernelGGL((k_board_pass<TM, PD, kGatherBounded>), dim3(grid), dim3(64), 0, st, a, g);
   else if ((a.C & 31) == 0)
     hipLaunchKernelGGL((k_board_pass<TM, PD, kGatherAligned>), dim3(grid), dim3(64), 0, st, a, g);
@@ -869,10 +902,13 @@ static hipError_t launch_board_pass_t(const PassArgs& a, const GridGeom& g, bool
 }
 
 // One band per wave; (T, pd) must satisfy pass_config_compiled(kLayoutBand, ...).
-// bounded: cells beyond the board's edges are dead (no torus).
+// bounded: cells beyond the board's edges are dead (no torus).  top / bot
+// non-null: the R rows are a strip with T halo rows in each (pass of T
+// generations, the result for the strip's rows only).
 hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
-                             int32_t D, const GridGeom& g, int pd, bool bounded, hipStream_t st) {
-  PassArgs a{src, dst, R, C, D};
+                             int32_t D, const GridGeom& g, int pd, bool bounded, hipStream_t st,
+                             const uint32_t* top, const uint32_t* bot) {
+  PassArgs a{src, dst, R, C, D, top, bot};
 #define GOL_LAUNCH_BAND(TV, PDV) \
   if (T == TV && pd == PDV) return launch_board_pass_t<TV, PDV>(a, g, bounded, st);
   GOL_LAUNCH_BAND(1, 3)
@@ -896,7 +932,7 @@ hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t 
 // and the board must be smaller than 2 GiB.
 hipError_t launch_board_pass_half(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
                                   int32_t D, const GridGeom& g, int pd, hipStream_t st) {
-  PassArgs a{src, dst, R, C, D};
+  PassArgs a{src, dst, R, C, D, nullptr, nullptr};
   const int nitems = g.nstrips * (g.nbands / 2);
   const int grid = ((nitems + 7) / 8) * 8;
 #define GOL_LAUNCH_HALF(TV, PDV)                                                          \

@@ -204,3 +204,33 @@ def test_bounded_board_rejects_the_paired_layout():
     rc = gol.lib().gol_step_packed_bounded(fake, 64, 128, 5, fake, None, ctypes.byref(c))
     assert rc == -1
     assert b"band layout" in gol.lib().gol_last_error()
+
+
+@pytest.mark.parametrize("t,cfg,needle", [
+    (3, None, b"t must be"), (0, None, b"t must be"), (-1, None, b"generations"),
+    (17, None, b"t must be"),
+    (8, gol.PassConfig(12, 0, 0, 0), b"t_block"), (8, gol.PassConfig(0, 0, 0, 2), b"band layout"),
+    (8, gol.PassConfig(0, -1, 0, 0), b"negative"), (8, gol.PassConfig(0, 0, 4, 0), b"prefetch"),
+])
+def test_strip_pass_rejects_bad_arguments(t, cfg, needle):
+    """Rejected before any device work (the pointers are never dereferenced)."""
+    fake = [ctypes.c_void_p(0x100000 * k) for k in range(1, 5)]
+    L = gol.lib()
+    rc = L.gol_strip_pass(fake[0], fake[1], fake[2], 64, 128, t, fake[3], None,
+                          ctypes.byref(cfg) if cfg is not None else None)
+    assert rc == -1
+    assert needle in L.gol_last_error(), L.gol_last_error()
+
+
+def test_strip_pass_rejects_null_and_overlap():
+    L = gol.lib()
+    a, b, c, d = (ctypes.c_void_p(0x1000000 * k) for k in range(1, 5))
+    assert L.gol_strip_pass(None, b, c, 64, 128, 4, d, None, None) == -1
+    assert L.gol_strip_pass(a, None, c, 64, 128, 4, d, None, None) == -1
+    assert L.gol_strip_pass(a, b, None, 64, 128, 4, d, None, None) == -1
+    assert L.gol_strip_pass(a, b, c, 64, 128, 4, None, None, None) == -1
+    assert L.gol_strip_pass(a, b, c, 0, 128, 4, d, None, None) == -1
+    # 64 rows x 2 words = 1 KiB strip; outputs that touch the strip or a halo
+    for out in (0x1000000, 0x1000000 + 1016, 0x2000000 + 8, 0x3000000 - 1000):
+        rc = L.gol_strip_pass(a, b, c, 64, 128, 4, ctypes.c_void_p(out), None, None)
+        assert rc == -1 and b"overlaps" in L.gol_last_error(), hex(out)

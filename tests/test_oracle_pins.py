@@ -333,3 +333,75 @@ def test_bounded_block_in_a_corner():
     b = np.zeros((6, 6), dtype=np.uint8)
     b[:2, :2] = 1
     assert np.array_equal(oracle.ref.life_bounded(b, 9), b)
+
+
+# ---------------------------------------------------------------------------
+# Strip pass (a row strip of a larger torus with t halo rows on each side)
+# ---------------------------------------------------------------------------
+def torus_strip(board, a, rows, t):
+    """Strip rows a .. a + rows - 1 of a torus and its t halo rows each side,
+    every index taken modulo the torus's row count."""
+    R = board.shape[0]
+    idx = lambda lo, n: [(lo + k) % R for k in range(n)]
+    return board[idx(a, rows)], board[idx(a - t, t)], board[idx(a + rows, t)]
+
+
+@pytest.mark.parametrize("R,C,a,rows,t", [(12, 9, 3, 4, 1), (12, 9, 3, 4, 3), (10, 7, 8, 5, 2),
+                                          (9, 5, 0, 9, 4), (16, 11, 5, 2, 6), (7, 3, 6, 1, 9),
+                                          (20, 64, 17, 6, 5)])
+def test_strip_pass_is_a_slice_of_the_torus(R, C, a, rows, t):
+    """With halo rows taken from the torus, the strip after t generations is
+    the torus's own rows a .. a + rows - 1 (mod R) after t generations, also
+    where the strip or its halos cross row 0 and where t exceeds the strip's
+    height or the torus's."""
+    for k in range(4):
+        b = seeded_inputs.board_bytes(557, 100 * k + R + C + a, R, C, 0.4)
+        strip, top, bottom = torus_strip(b, a, rows, t)
+        want = oracle.ref.life(b, t)[[(a + i) % R for i in range(rows)]]
+        assert np.array_equal(oracle.ref.strip_pass(strip, top, bottom, t), want), (k,)
+
+
+def test_strip_pass_one_generation_cell_by_cell():
+    """t = 1 with unrelated halo rows, against an explicit loop: row -1 is
+    top, row rows is bottom, columns wrap."""
+    rows, C = 5, 7
+    for k in range(6):
+        s = seeded_inputs.board_bytes(558, k, rows, C, 0.5)
+        top = seeded_inputs.board_bytes(558, 100 + k, 1, C, 0.5)
+        bot = seeded_inputs.board_bytes(558, 200 + k, 1, C, 0.5)
+
+        def cell(r, c):
+            if r < 0:
+                return int(top[0, c % C])
+            if r >= rows:
+                return int(bot[0, c % C])
+            return int(s[r, c % C])
+        want = np.zeros((rows, C), dtype=np.uint8)
+        for r in range(rows):
+            for c in range(C):
+                n = sum(cell(r + dr, c + dc) for dr in (-1, 0, 1) for dc in (-1, 0, 1)
+                        if dr or dc)
+                want[r, c] = 1 if n == 3 or (s[r, c] and n == 2) else 0
+        assert np.array_equal(oracle.ref.strip_pass(s, top, bot, 1), want), k
+
+
+def test_strip_pass_light_cone():
+    """The farthest halo row (t rows away) reaches only the strip's edge row:
+    changing it leaves every other row as it was, and changes the edge row for
+    some boards."""
+    rows, C, t = 8, 20, 3
+    changed = 0
+    for k in range(20):
+        s = seeded_inputs.board_bytes(559, k, rows, C, 0.45)
+        top = seeded_inputs.board_bytes(559, 100 + k, t, C, 0.45)
+        bot = seeded_inputs.board_bytes(559, 200 + k, t, C, 0.45)
+        base = oracle.ref.strip_pass(s, top, bot, t)
+        top2 = top.copy()
+        top2[0] ^= 1
+        bot2 = bot.copy()
+        bot2[-1] ^= 1
+        up = oracle.ref.strip_pass(s, top2, bot, t)
+        down = oracle.ref.strip_pass(s, top, bot2, t)
+        assert np.array_equal(up[1:], base[1:]) and np.array_equal(down[:-1], base[:-1])
+        changed += int(not np.array_equal(up[0], base[0])) + int(not np.array_equal(down[-1], base[-1]))
+    assert changed > 0
