@@ -13,7 +13,9 @@ board), c5 (Poisson request stream through the continuous-batching server vs
 a one-at-a-time server), pop (population counting: the kernel on the 65536^2
 board and Table 1's checks on the 16384^2 run), bounded (the 16384^2 board
 with dead surroundings instead of the torus), strip (one GPU's 8192 x 65536
-share of the 65536^2 board, halo rows from separate buffers), copy (copy-kernel calibration of
+share of the 65536^2 board, halo rows from separate buffers), decomp (Table
+2's largest case on the GPU, with the CPU study of the row, column and 2-D
+decompositions as its baseline), copy (copy-kernel calibration of
 the traffic counters).
 """
 from __future__ import annotations
@@ -97,12 +99,13 @@ def measured_traffic(record: str, cfg=None):
     return rec["hbm_bytes_per_launch"]
 
 
-def kernel_name(cfg):
-    """The tile-pass kernel a launch configuration runs."""
+def kernel_name(cfg, cols=16384):
+    """The tile-pass kernel a launch configuration runs on a torus of `cols`
+    columns (gather 1: whole dwords, 0: rows that end inside a dword)."""
     T, pd = cfg["t_block"], cfg["prefetch"]
     if cfg["layout"] == 2:
         return f"k_board_pass_half<{T}, {pd}>"
-    return f"k_board_pass<{T}, {pd}, true>"
+    return f"k_board_pass<{T}, {pd}, {1 if cols % 32 == 0 else 0}>"
 
 
 def roofline_alu(cells, cfg, avg_launch_s):
@@ -120,7 +123,7 @@ def roofline_hbm(cells, avg_launch_s):
     achieved = by / avg_launch_s / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
             "frac": achieved / (HBM_PEAK_BYTES / 1e9), "traffic": None,
-            "kernel": "k_board_pass<1, 3, true>", "avg_launch_us": avg_launch_s * 1e6,
+            "kernel": "k_board_pass<1, 3, 1>", "avg_launch_us": avg_launch_s * 1e6,
             "bytes_per_launch": by}
 
 
@@ -629,6 +632,84 @@ def strip_workload(args):
     print(json.dumps(line), flush=True)
 
 
+# Table 2: seconds on the paper's four-thread machine, 1-D decomposition
+PAPER_TABLE2_S = {
+    (120, 60, 500): (28.144, 18.252, 13.630, 11.214),
+    (120, 60, 1000): (54.384, 34.561, 28.398, 26.567),
+    (120, 60, 2000): (108.633, 85.531, 36.824, 35.971),
+    (240, 120, 500): (108.674, 77.034, 49.174, 41.638),
+    (240, 120, 1000): (218.939, 125.108, 94.846, 67.993),
+    (240, 120, 2000): (436.149, 261.167, 156.326, 126.420),
+}
+
+
+def cpu_decomposition_study(p, seed):
+    """The CPU-baseline leg of the decomp workload: the oracle with the row,
+    column and 2-D block decompositions (Sections 2.1-2.2) at Table 2's scales,
+    iteration counts and thread counts, and on a 4096^2 board where a
+    generation is large enough for the split to matter more than the fork."""
+    import oracle
+    import seeded_inputs
+    maxt = cpu_threads()
+    threads = sorted({1, 2, 4, 8, maxt})
+    table = []
+    for (w, h, it) in PAPER_TABLE2_S:
+        b = seeded_inputs.board_bytes(seed, 0, h, w, p)
+        row = {"cols": w, "rows": h, "iterations": it, "paper_s": PAPER_TABLE2_S[(w, h, it)]}
+        for d in ("rows", "cols", "2d"):
+            row[d + "_s"] = {}
+            for t in threads:
+                t0 = time.perf_counter()
+                oracle.life_decomp(b, it, t, d)
+                row[d + "_s"][t] = time.perf_counter() - t0
+        table.append(row)
+    big = seeded_inputs.board_bytes(seed, 1, 4096, 4096, p)
+    large = {"rows": 4096, "cols": 4096, "iterations": 20}
+    for d in ("rows", "cols", "2d"):
+        large[d + "_cu_per_s"] = {}
+        for t in threads:
+            t0 = time.perf_counter()
+            oracle.life_decomp(big, 20, t, d)
+            large[d + "_cu_per_s"][t] = 4096 * 4096 * 20 / (time.perf_counter() - t0)
+    return table, large, maxt
+
+
+def decomp_workload(args):
+    """Table 2's largest case (240 x 120 cells, 2000 iterations) on the GPU,
+    with the CPU decomposition study (rows, columns, 2-D) as the baseline."""
+    import torch
+    import paper_1209_4408_amd as gol
+    import seeded_inputs
+    w, h, G, p = 240, 120, 2000, 0.3
+    words = seeded_inputs.board_packed(SEED, 0, h, w, p)
+    d_in = torch.from_numpy(words.view(np.int64)).cuda()
+    d_out = torch.empty_like(d_in)
+    for _ in range(args.warmup):
+        gol.step_packed(d_in, h, w, G, d_out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gol.step_packed(d_in, h, w, G, d_out)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    table, large, maxt = cpu_decomposition_study(p, SEED)
+    last = table[-1]
+    rows_s = last["rows_s"][maxt]
+    line = {"metric": "cell-updates/sec", "value": w * h * G * args.steps / wall,
+            "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {"workload": "Table 2's largest case: 240 x 120 torus (240 columns), "
+                                   "Bernoulli(0.3), 2000 iterations", "rows": h, "cols": w,
+                       "generations": G, "p": p, "seed": SEED, "parallelism": "single GPU"},
+            "roofline": None,
+            "cpu_baseline": {"value": w * h * G / rows_s, "unit": "cell-updates/s",
+                             "cores": maxt, "kind": "oracle",
+                             "sample": f"the whole run, row decomposition, {maxt} OpenMP threads"},
+            "cpu_decomposition_study": {"table2": table, "large": large}}
+    print(json.dumps(line), flush=True)
+
+
 def sweep(args):
     """Single-board tuning sweep: generations per pass x band count x prefetch.
     Band counts put the wave total just under a multiple of the SIMD count."""
@@ -664,7 +745,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2",
                     choices=["c1", "c2", "c3", "c4", "c5", "copy", "pop", "bounded",
-                             "strip"])
+                             "strip", "decomp"])
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=2700.0,
                     help="Poisson arrival rate; requests average 1.08e10 cell-updates, so "
@@ -736,6 +817,9 @@ def main():
         return
     elif args.workload == "strip":
         strip_workload(args)
+        return
+    elif args.workload == "decomp":
+        decomp_workload(args)
         return
     ms = res["wall_s"] / args.steps * 1e3
     line = {

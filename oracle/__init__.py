@@ -14,7 +14,9 @@ Contents:
     (cell (r, c) is bit c mod 64 of word r * W + c // 64, LSB first,
     W = ceil(C / 64), padding bits 0), written with ``numpy.packbits``;
   * ``torus_window``: a wrapped sub-board, for light-cone checks of large runs;
-  * ``population_at``: live cells after chosen generation counts (Table 1).
+  * ``population_at``: live cells after chosen generation counts (Table 1);
+  * ``life_decomp``: the C oracle with the paper's row, column or 2-D block
+    decomposition over OpenMP threads (Sections 2.1-2.2), for the CPU study.
 """
 from __future__ import annotations
 
@@ -54,6 +56,9 @@ def _load():
         lib.oracle_life_omp.restype = ctypes.c_int
         lib.oracle_life_omp.argtypes = [ctypes.c_void_p, i64, i64, i64, ctypes.c_void_p,
                                         ctypes.c_int]
+        lib.oracle_life_decomp.restype = ctypes.c_int
+        lib.oracle_life_decomp.argtypes = [ctypes.c_void_p, i64, i64, i64, ctypes.c_void_p,
+                                           ctypes.c_int, ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -75,6 +80,27 @@ def life(board: np.ndarray, generations: int, threads: int = 1) -> np.ndarray:
                                      int(threads))
     else:
         rc = _load().oracle_life(b.ctypes.data, R, C, int(generations), out.ctypes.data)
+    if rc == -1:
+        raise ValueError("invalid arguments")
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    return out
+
+
+DECOMPOSITIONS = {"rows": 0, "cols": 1, "2d": 2}
+
+
+def life_decomp(board: np.ndarray, generations: int, threads: int, decomposition: str) -> np.ndarray:
+    """The C oracle with each generation split among ``threads`` OpenMP
+    threads by rows (Figure 1), columns (Figure 2) or an m x n grid of
+    sub-regions (Figure 3, m n = threads, as square as threads allows)."""
+    b = np.ascontiguousarray(board, dtype=np.uint8)
+    if b.ndim != 2:
+        raise ValueError("board must be 2-D")
+    out = np.empty_like(b)
+    R, C = b.shape
+    rc = _load().oracle_life_decomp(b.ctypes.data, R, C, int(generations), out.ctypes.data,
+                                    int(threads), DECOMPOSITIONS[decomposition])
     if rc == -1:
         raise ValueError("invalid arguments")
     if rc != 0:
