@@ -98,11 +98,21 @@ int gol_step_packed_ex(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t
  *             towards each other and trade the rows of their shared edge,
  *             so only the outer edges of the pair recompute halo rows;
  *             needs t_block 8, 12 or 16, cols % 32 == 0, a packed board
- *             below 2 GiB and bands of at least t_block rows.
+ *             below 2 GiB and bands of at least t_block rows;
+ *             GOL_LAYOUT_RESIDENT: the whole board in one workgroup's LDS
+ *             for all its generations (one launch per run, or per
+ *             population check), for boards whose two generations fit
+ *             in 64 KiB of LDS: cols <= 32768 and rows x ceil(cols / 32)
+ *             dwords plus one pad dword per row segment (at most 1024) at
+ *             most 8192 -- every board of up to 7168 dwords fits; t_block,
+ *             band_rows and prefetch are ignored.  With
+ *             every field 0 it is taken for boards of at most 1024 such
+ *             dwords (e.g. 128 x 256) unless the autotuner chose otherwise.
  * Combinations outside these sets -> GOL_EINVAL with a message.
  */
 #define GOL_LAYOUT_BAND 1
 #define GOL_LAYOUT_PAIRED 2
+#define GOL_LAYOUT_RESIDENT 3
 typedef struct gol_pass_config {
   int32_t t_block;
   int32_t band_rows;

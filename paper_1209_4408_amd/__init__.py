@@ -179,6 +179,7 @@ def empty_packed(rows: int, cols: int, device="cuda"):
 
 LAYOUT_BAND = 1
 LAYOUT_PAIRED = 2
+LAYOUT_RESIDENT = 3  # whole board in one workgroup's LDS for a run (small boards)
 
 
 def step_packed(d_in, rows: int, cols: int, generations: int, d_out=None, stream=None,

@@ -28,6 +28,8 @@ hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t 
                              const uint32_t* top = nullptr, const uint32_t* bot = nullptr);
 hipError_t launch_board_pass_half(int T, const uint32_t* src, uint32_t* dst, int32_t R, int32_t C,
                                   int32_t D, const GridGeom& g, int pd, hipStream_t st);
+hipError_t launch_board_lds(const uint32_t* src, uint32_t* dst, int32_t R, int32_t C, int32_t D,
+                            int32_t G, hipStream_t st);
 hipError_t launch_population(const uint64_t* b, int64_t R, int64_t C, unsigned long long* out,
                              hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
@@ -179,6 +181,17 @@ static bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t b
 }
 
 int default_T() { return 12; }
+
+// Boards the resident layout takes when no t_block or layout is asked for:
+// at most this many dwords, where a tile pass is bound by its launch and by
+// one wave's sweep rather than by its work (on MI355X, 120 generations: 64^2
+// 33 us resident against 77 us in tile passes, 128^2 41 against 77,
+// 120 x 240 60 against 90; 256^2 83 against 77, where one workgroup's share
+// of the chip starts to bind).
+constexpr int64_t kResidentAutoDwords = 1024;
+static bool resident_auto(int64_t R, int64_t C) {
+  return resident_fits(R, C) && R * ((C + 31) / 32) <= kResidentAutoDwords;
+}
 int default_batch_T() { return 16; }
 
 // Band height of batched schedules (tiles of many boards share a level).
@@ -221,11 +234,23 @@ int resolve_config(int64_t R, int64_t C, const PassConfig& want, PassConfig* out
   if (c.bounded && c.layout != 0 && c.layout != kLayoutBand)
     return set_error(GOL_EINVAL, "a bounded board runs in the band layout (layout 0 or 1)");
   PassConfig tc;
-  if (!want.bounded && want.T == 0 && want.layout == 0 && tuned_choice(R, C, &tc)) {
+  const bool automatic = !want.bounded && want.T == 0 && want.layout == 0;
+  const bool tuned = automatic && tuned_choice(R, C, &tc);
+  if (tuned) {
     c.T = tc.T;
     c.layout = tc.layout;
     if (!c.band_rows) c.band_rows = tc.band_rows;
     if (!c.pd) c.pd = tc.pd;
+  }
+  if (c.layout == kLayoutResident || (automatic && !tuned && resident_auto(R, C))) {
+    if (!resident_fits(R, C))
+      return set_error(GOL_EINVAL,
+                       "the resident layout needs cols <= 32768 and both generations of the "
+                       "board within %lld bytes of LDS",
+                       (long long)kResidentMaxLdsBytes);
+    c.layout = kLayoutResident;
+    *out = c;
+    return GOL_OK;
   }
   if (!c.T) c.T = default_T();
   if (!c.layout) c.layout = kLayoutBand;
@@ -233,7 +258,8 @@ int resolve_config(int64_t R, int64_t C, const PassConfig& want, PassConfig* out
   if (!valid_board_T(c.T))
     return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8, 12 or 16 (got %d)", c.T);
   if (c.layout != kLayoutBand && c.layout != kLayoutPaired)
-    return set_error(GOL_EINVAL, "layout must be 0, 1 (band) or 2 (paired) (got %d)", c.layout);
+    return set_error(GOL_EINVAL, "layout must be 0, 1 (band), 2 (paired) or 3 (resident) (got %d)",
+                     c.layout);
   if (!pass_config_compiled(c.layout, c.T, c.pd))
     return set_error(GOL_EINVAL, "prefetch %d is not built for layout %d with t_block %d", c.pd,
                      c.layout, c.T);
@@ -252,6 +278,8 @@ int resolve_config(int64_t R, int64_t C, const PassConfig& want, PassConfig* out
 hipError_t launch_pass(const PassConfig& c, const uint32_t* src, uint32_t* dst, int64_t R,
                        int64_t C, hipStream_t st) {
   const int32_t D = (int32_t)(2 * ((C + 63) / 64));
+  if (c.layout == kLayoutResident)  // c.T generations in one launch
+    return launch_board_lds(src, dst, (int32_t)R, (int32_t)C, D, c.T, st);
   if (c.layout == kLayoutPaired)
     return launch_board_pass_half(c.T, src, dst, (int32_t)R, (int32_t)C, D,
                                   paired_geometry(R, C, c.band_rows, c.T, c.pd), c.pd, st);
@@ -294,7 +322,12 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
   int64_t g = 0;
   for (int64_t i = 0; i <= ncheck; ++i) {
     const int64_t upto = i < ncheck ? checks[i] : G;
-    if (upto > g) {
+    if (upto > g && c.layout == kLayoutResident) {
+      // one launch runs all the generations up to the next check
+      for (int64_t left = upto - g; left > 0; left -= std::min<int64_t>(left, 1 << 30))
+        ops.push_back(Op{(int)std::min<int64_t>(left, 1 << 30), -1});
+      g = upto;
+    } else if (upto > g) {
       for (int t : single_board_passes(upto - g, c.T)) ops.push_back(Op{t, -1});
       g = upto;
     }
@@ -307,6 +340,22 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
     for (const Op& o : ops)
       if (e == hipSuccess) e = launch_population(d_out, R, C, counts + o.slot, st);
     return e == hipSuccess ? GOL_OK : hip_error(e, "copy kernel launch");
+  }
+  if (c.layout == kLayoutResident) {
+    // each launch reads its whole board before writing, so every launch
+    // after the first runs in place on d_out
+    const int32_t D = (int32_t)(2 * W);
+    const uint32_t* cur = (const uint32_t*)d_in;
+    for (const Op& o : ops) {
+      if (e != hipSuccess) break;
+      if (o.T == 0) {
+        e = launch_population((const uint64_t*)cur, R, C, counts + o.slot, st);
+        continue;
+      }
+      e = launch_board_lds(cur, (uint32_t*)d_out, (int32_t)R, (int32_t)C, D, o.T, st);
+      cur = (const uint32_t*)d_out;
+    }
+    return e == hipSuccess ? GOL_OK : hip_error(e, "resident board launch");
   }
   void* s1v = nullptr;
   rc = scratch_alloc(&s1v, bytes, st);

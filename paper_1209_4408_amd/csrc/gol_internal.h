@@ -24,6 +24,34 @@ constexpr int kHalfStripDwords = kWave / 2 - 2;
 // Layouts of the single-board tile pass.
 constexpr int kLayoutBand = 1;    // one band of one strip per wave
 constexpr int kLayoutPaired = 2;  // two adjacent bands per wave, sharing their edge
+constexpr int kLayoutResident = 3;  // whole board in one workgroup's LDS for a whole run
+
+// Resident layout: threads of its workgroup, and the LDS it may use for the
+// board's two generations (rows of ceil(C / 32) dwords each).
+constexpr int kResidentThreads = 1024;
+constexpr int64_t kResidentMaxLdsBytes = 65536;
+// Resident layout geometry.  The workgroup has about one thread per dword on
+// the smallest boards and kResidentThreads beyond (never fewer threads than
+// dwords in a row); thread t owns dword column t mod nd of a segment of rs
+// consecutive rows.  In LDS each segment is followed by one pad dword, so the
+// segments a wave sweeps start in different banks.
+struct ResidentGeom {
+  int64_t nd, threads, nsegs, rs, words;  // words: one generation, pads included
+};
+constexpr ResidentGeom resident_geom(int64_t R, int64_t C) {
+  const int64_t nd = (C + 31) / 32;
+  const int64_t want = R * nd > nd ? R * nd : nd;
+  const int64_t t = ((want + 63) / 64) * 64;
+  const int64_t threads = t < kResidentThreads ? t : kResidentThreads;
+  const int64_t nsegs = threads / (nd > 0 ? nd : 1);
+  const int64_t rs = nsegs > 0 ? (R + nsegs - 1) / nsegs : R;
+  return ResidentGeom{nd, threads, nsegs, rs, R * nd + (R - 1) / (rs > 0 ? rs : 1) + 1};
+}
+// Rows of at most kResidentThreads dwords; both generations within the LDS budget.
+constexpr bool resident_fits(int64_t R, int64_t C) {
+  return (C + 31) / 32 <= kResidentThreads &&
+         resident_geom(R, C).words * 8 <= kResidentMaxLdsBytes;
+}
 
 // Prefetch distances (rows) compiled for each layout and pass length.
 constexpr bool pass_config_compiled(int layout, int T, int pd) {

@@ -879,6 +879,85 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int6
 }
 
 // ---------------------------------------------------------------------------
+// Small boards: the whole board resident in one workgroup's LDS for a run.
+//
+// The packed board is read once into LDS (rows of nd = ceil(C / 32) dwords,
+// padding bits cleared), then every generation is computed from one LDS copy
+// into the other, with a workgroup barrier between generations, and the last
+// one is written out once: no HBM traffic and no launch per pass, which is
+// what bounds the tile passes on boards this small.  Work item (column j,
+// row segment s) sweeps its rows downwards keeping the horizontal sums of the
+// rows above, at and below the current one in registers; the word-edge bits
+// come from the neighbouring dwords in LDS, wrapping at the row end (the
+// column after C - 1 is column 0), and rows wrap modulo R.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kResidentThreads) void k_board_lds(const uint32_t* src, uint32_t* dst,
+                                                                int32_t R, int32_t C, int32_t D,
+                                                                int32_t G) {
+  extern __shared__ uint32_t lds_board[];
+  const int nd = (C + 31) >> 5;  // <= the workgroup's thread count
+  const int nthreads = (int)blockDim.x;
+  const int nsegs = nthreads / nd;
+  const int rs = (R + nsegs - 1) / nsegs;
+  const int nbuf = R * nd + (R - 1) / rs + 1;  // one generation with its segment pads
+  auto base = [&](int r) { return r * nd + r / rs; };
+  uint32_t* cur = lds_board;
+  uint32_t* nxt = lds_board + nbuf;
+  const int tid = (int)threadIdx.x;
+  const uint32_t last_mask = (C & 31) ? (1u << (C & 31)) - 1u : 0xFFFFFFFFu;
+  for (int i = tid; i < R * nd; i += nthreads) {
+    const int r = i / nd, j = i - r * nd;
+    const uint32_t v = ((GlobalIn)src)[(int64_t)r * D + j];
+    cur[base(r) + j] = j == nd - 1 ? v & last_mask : v;
+  }
+  // this thread's work item: dword column j of rows r0 .. r1 - 1 (segment s)
+  const int j = tid % nd, s = tid / nd;
+  const int r0 = s * rs, r1 = min(R, r0 + rs);
+  const bool active = s < nsegs && r0 < r1;
+  const int n = min(32, C - 32 * j);  // cells in dword j
+  const uint32_t mask = n == 32 ? 0xFFFFFFFFu : (1u << n) - 1u;
+  const int cl = (32 * j - 1 + C) % C;  // the cell west of the dword's first
+  const int cr = (32 * j + n) % C;      // the cell east of its last
+  const int jl = cl >> 5, bl = cl & 31, jr = cr >> 5, br = cr & 31;
+  const int above = base(r0 == 0 ? R - 1 : r0 - 1);  // rows of other segments
+  const int below = base(r1 == R ? 0 : r1);
+  const int own = s;                                 // pads before row r0's segment
+  __syncthreads();
+  for (int g = 0; g < G; ++g) {
+    if (active) {
+      uint32_t lo[3], hi[3], x[3];
+      auto hsum = [&](int b, int k) {
+        const uint32_t* row = cur + b;
+        const uint32_t v = row[j];
+        const uint32_t w = (row[jl] >> bl) & 1u, e = (row[jr] >> br) & 1u;
+        const uint32_t xl = ((v << 1) | w) & mask;      // west neighbours
+        const uint32_t xr = (v >> 1) | (e << (n - 1));  // east neighbours
+        lo[k] = xor3(xl, v, xr);
+        hi[k] = maj3(xl, v, xr);
+        x[k] = v;
+      };
+      hsum(above, 0);
+      hsum(r0 * nd + own, 1);
+      for (int r = r0; r < r1; ++r) {
+        hsum(r + 1 < r1 ? (r + 1) * nd + own : below, 2);
+        nxt[r * nd + own + j] =
+            life_rule(lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], x[1]) & mask;
+        lo[0] = lo[1]; hi[0] = hi[1];
+        lo[1] = lo[2]; hi[1] = hi[2]; x[1] = x[2];
+      }
+    }
+    __syncthreads();
+    uint32_t* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+  for (int i = tid; i < R * D; i += nthreads) {
+    const int r = i / D, jj = i - r * D;
+    ((GlobalOut)dst)[(int64_t)r * D + jj] = jj < nd ? cur[base(r) + jj] : 0u;  // padding: 0
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Host-side launchers (called by the C ABI in gol_capi.cpp).
 // ---------------------------------------------------------------------------
 template <int TM, int PD>
@@ -925,6 +1004,17 @@ hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t 
   GOL_LAUNCH_BAND(16, 12)
 #undef GOL_LAUNCH_BAND
   return hipErrorInvalidValue;
+}
+
+// Whole board resident in LDS for G generations; resident_fits(R, C) must
+// hold.  src may equal dst (the board is read in full before any write).
+hipError_t launch_board_lds(const uint32_t* src, uint32_t* dst, int32_t R, int32_t C, int32_t D,
+                            int32_t G, hipStream_t st) {
+  const ResidentGeom rg = resident_geom(R, C);
+  const size_t lds = (size_t)2 * (size_t)rg.words * 4u;
+  hipLaunchKernelGGL(k_board_lds, dim3(1), dim3((unsigned)rg.threads), lds, st, src, dst, R, C, D,
+                     G);
+  return hipGetLastError();
 }
 
 // Two bands per wave; (T, pd) must satisfy pass_config_compiled(kLayoutPaired,

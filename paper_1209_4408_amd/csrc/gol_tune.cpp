@@ -45,6 +45,7 @@ std::map<Key, PassConfig> g_table;
 bool g_loaded = false;
 
 bool usable(const PassConfig& c) {
+  if (c.layout == kLayoutResident) return true;
   return valid_board_T(c.T) && c.band_rows > 0 &&
          (c.layout == kLayoutBand || c.layout == kLayoutPaired) &&
          pass_config_compiled(c.layout, c.T, c.pd);
@@ -106,6 +107,14 @@ std::vector<PassConfig> candidates(int64_t R, int64_t C, int nsimd) {
         out.push_back(c);
       }
     }
+  }
+  if (resident_fits(R, C)) {
+    // the whole board in one workgroup's LDS, timed over launches of 12
+    // generations (a run is one launch whatever its length)
+    PassConfig c;
+    c.T = 12;
+    c.layout = kLayoutResident;
+    out.push_back(c);
   }
   return out;
 }

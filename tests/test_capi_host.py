@@ -154,7 +154,7 @@ def test_plan_rejects_bad_input():
 
 @pytest.mark.parametrize("cfg", [dict(t_block=5), dict(t_block=12, layout=2),   # cols % 32 != 0
                                  dict(t_block=4, layout=2), dict(t_block=16, prefetch=3),
-                                 dict(t_block=8, prefetch=12), dict(layout=3),
+                                 dict(t_block=8, prefetch=12), dict(layout=4),
                                  dict(band_rows=-2), dict(t_block=16, layout=2, prefetch=6)])
 def test_pass_config_rejected_before_any_device_work(cfg):
     """gol_step_packed_cfg checks the launch configuration on the host; the
@@ -234,3 +234,15 @@ def test_strip_pass_rejects_null_and_overlap():
     for out in (0x1000000, 0x1000000 + 1016, 0x2000000 + 8, 0x3000000 - 1000):
         rc = L.gol_strip_pass(a, b, c, 64, 128, 4, ctypes.c_void_p(out), None, None)
         assert rc == -1 and b"overlaps" in L.gol_last_error(), hex(out)
+
+
+def test_resident_layout_rejects_boards_beyond_its_lds_budget():
+    """rows x ceil(cols / 32) x 8 bytes must fit in 64 KiB (two generations)."""
+    fake = ctypes.c_void_p(0x1000)
+    L = gol.lib()
+    c = gol.PassConfig(0, 0, 0, gol.LAYOUT_RESIDENT)
+    rc = L.gol_step_packed_cfg(fake, 257, 1024, 5, ctypes.c_void_p(0x100000), None, ctypes.byref(c))
+    assert rc == -1 and b"resident" in L.gol_last_error()
+    c = gol.PassConfig(0, 0, 0, gol.LAYOUT_RESIDENT)
+    rc = L.gol_step_packed_bounded(fake, 64, 64, 5, ctypes.c_void_p(0x100000), None, ctypes.byref(c))
+    assert rc == -1 and b"band layout" in L.gol_last_error()

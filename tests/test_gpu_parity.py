@@ -233,7 +233,7 @@ def test_config_errors():
     for cfg in (dict(t_block=12, layout=gol.LAYOUT_PAIRED),          # C % 32 != 0
                 dict(t_block=4, layout=gol.LAYOUT_PAIRED),           # T not 8, 12, 16
                 dict(t_block=16, prefetch=3),                         # prefetch not built
-                dict(t_block=5), dict(layout=3), dict(band_rows=-1)):
+                dict(t_block=5), dict(layout=4), dict(band_rows=-1)):
         with pytest.raises(gol.GolError) as e:
             gol.step_packed(d, R, C, 5, config=cfg)
         assert e.value.code == -1, cfg
