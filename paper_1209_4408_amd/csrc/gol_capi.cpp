@@ -401,8 +401,37 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
   return GOL_OK;
 }
 
-// Library streams for the synchronous host API.
+// Library streams for the synchronous host API, each with a pinned host
+// staging buffer that its calls reuse (a call holds the slot until its
+// stream has drained, so the buffer is never in use twice).
+struct HostSlot {
+  hipStream_t st = nullptr;
+  void* pinned = nullptr;
+  size_t cap = 0;
+};
 static std::mutex g_stream_mu;
+static std::vector<HostSlot> g_slots;
+
+static int acquire_slot(HostSlot* slot) {
+  {
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    if (!g_slots.empty()) {
+      *slot = g_slots.back();
+      g_slots.pop_back();
+      return GOL_OK;
+    }
+  }
+  *slot = HostSlot{};
+  hipError_t e = hipStreamCreateWithFlags(&slot->st, hipStreamNonBlocking);
+  return e == hipSuccess ? GOL_OK : hip_error(e, "hipStreamCreate");
+}
+
+static void release_slot(const HostSlot& slot) {
+  std::lock_guard<std::mutex> lk(g_stream_mu);
+  g_slots.push_back(slot);
+}
+
+// Library streams without staging (the second stream of batched schedules).
 static std::vector<hipStream_t> g_streams;
 
 static int acquire_stream(hipStream_t* st) {
@@ -423,6 +452,10 @@ static void release_stream(hipStream_t st) {
   g_streams.push_back(st);
 }
 
+// Byte boards up to this size go through the slot's pinned buffer (a host
+// copy and one DMA each way); larger ones are copied from pageable memory.
+constexpr size_t kStagingMaxBytes = (size_t)16 << 20;
+
 int step_host(const uint8_t* board, int64_t R, int64_t C, int64_t G, uint8_t* out, int T) {
   int rc = check_board(R, C, G);
   if (rc) return rc;
@@ -433,16 +466,26 @@ int step_host(const uint8_t* board, int64_t R, int64_t C, int64_t G, uint8_t* ou
     return set_error(GOL_EINVAL, "board and out partially overlap");
   const int64_t W = (C + 63) / 64;
   const size_t words_bytes = (size_t)(R * W * 8);
-  hipStream_t st;
-  rc = acquire_stream(&st);
+  HostSlot slot;
+  rc = acquire_slot(&slot);
   if (rc) return rc;
+  const hipStream_t st = slot.st;
+  if (N <= kStagingMaxBytes && slot.cap < N) {
+    if (slot.pinned) (void)hipHostFree(slot.pinned);
+    slot.pinned = nullptr;
+    slot.cap = 0;
+    if (hipHostMalloc(&slot.pinned, N, 0) == hipSuccess) slot.cap = N;
+    else slot.pinned = nullptr;  // fall back to pageable copies
+  }
+  const bool staged = N <= kStagingMaxBytes && slot.cap >= N;
+  if (staged) memcpy(slot.pinned, board, N);
   void *db = nullptr, *pa = nullptr, *pb = nullptr;
   rc = scratch_alloc(&db, N, st);
   if (!rc) rc = scratch_alloc(&pa, words_bytes, st);
   if (!rc) rc = scratch_alloc(&pb, words_bytes, st);
   hipError_t e = hipSuccess;
   if (!rc) {
-    e = hipMemcpyAsync(db, board, N, hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(db, staged ? slot.pinned : board, N, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = launch_pack((const uint8_t*)db, R, C, (uint64_t*)pa, st);
     if (e == hipSuccess) {
       PassConfig cfg;
@@ -450,7 +493,8 @@ int step_host(const uint8_t* board, int64_t R, int64_t C, int64_t G, uint8_t* ou
       rc = step_packed((const uint64_t*)pa, R, C, G, (uint64_t*)pb, st, cfg);
       if (!rc) {
         e = launch_unpack((const uint64_t*)pb, R, C, (uint8_t*)db, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(out, db, N, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(staged ? slot.pinned : out, db, N, hipMemcpyDeviceToHost, st);
       }
     }
   }
@@ -458,7 +502,8 @@ int step_host(const uint8_t* board, int64_t R, int64_t C, int64_t G, uint8_t* ou
   scratch_free(pa, st);
   scratch_free(db, st);
   hipError_t e2 = hipStreamSynchronize(st);
-  release_stream(st);
+  if (staged && !rc && e == hipSuccess && e2 == hipSuccess) memcpy(out, slot.pinned, N);
+  release_slot(slot);
   if (rc) return rc;
   if (e != hipSuccess) return hip_error(e, "gol_step");
   if (e2 != hipSuccess) return hip_error(e2, "hipStreamSynchronize");
