@@ -130,6 +130,31 @@ def test_host_byte_api_inplace_and_values():
     assert np.array_equal(b, want)
 
 
+def test_host_byte_api_from_several_threads():
+    """Concurrent gol_step calls each hold their own library stream and pinned
+    staging buffer; boards of growing sizes make the buffers grow too."""
+    import threading
+    boards = [rand_bytes(10, k, 40 + 37 * k, 50 + 61 * k, 0.4) for k in range(8)]
+    want = [oracle.life(b, 13) for b in boards]
+    errors = []
+
+    def worker(t):
+        try:
+            for rep in range(3):
+                for k in range(t % 2, len(boards), 2):
+                    if not np.array_equal(gol.step(boards[k], 13), want[k]):
+                        errors.append((t, rep, k))
+        except Exception as exc:  # reported below
+            errors.append((t, repr(exc)))
+    say("gol_step from 4 threads")
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+
+
 def test_device_pack_unpack_roundtrip():
     import torch
     R, C = 70, 333
