@@ -193,6 +193,19 @@ def test_autotuned_choice_is_used_and_exact():
         check(b, G, 0)  # t_block 0 takes the tuned choice
 
 
+def test_autotuner_times_the_resident_layout_on_small_boards():
+    """On a board the resident layout fits, it is one of the timed candidates;
+    whatever wins is then the default for that size and stays exact."""
+    for R, C, G in ((64, 64, 101), (200, 300, 50)):
+        cfg = gol.tune_config(R, C)
+        say("tuned", R, C, cfg)
+        assert cfg["layout"] in (gol.LAYOUT_BAND, gol.LAYOUT_PAIRED, gol.LAYOUT_RESIDENT)
+        b = rand_bytes(78, R, R, C, 0.4)
+        check(b, G, 0)
+        got = from_dev(gol.step_packed(to_dev(oracle.pack(b)), R, C, G, config=cfg))
+        assert np.array_equal(got, expect_words(b, G)), cfg
+
+
 # ---------------------------------------------------------------------------
 # Explicit launch configurations (gol_step_packed_cfg)
 # ---------------------------------------------------------------------------
