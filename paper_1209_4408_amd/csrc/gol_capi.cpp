@@ -189,6 +189,9 @@ int default_T() { return 12; }
 // 120 x 240 60 against 90; 256^2 83 against 77, where one workgroup's share
 // of the chip starts to bind).
 constexpr int64_t kResidentAutoDwords = 1024;
+// Generations per resident launch (about 0.1 s on the largest boards the
+// layout takes, well under that on the boards it is chosen for).
+constexpr int64_t kResidentMaxGens = 65536;
 static bool resident_auto(int64_t R, int64_t C) {
   return resident_fits(R, C) && R * ((C + 31) / 32) <= kResidentAutoDwords;
 }
@@ -323,9 +326,11 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
   for (int64_t i = 0; i <= ncheck; ++i) {
     const int64_t upto = i < ncheck ? checks[i] : G;
     if (upto > g && c.layout == kLayoutResident) {
-      // one launch runs all the generations up to the next check
-      for (int64_t left = upto - g; left > 0; left -= std::min<int64_t>(left, 1 << 30))
-        ops.push_back(Op{(int)std::min<int64_t>(left, 1 << 30), -1});
+      // one launch runs the generations up to the next check, at most
+      // kResidentMaxGens of them, so that no single launch holds the device
+      // for long
+      for (int64_t left = upto - g; left > 0; left -= std::min<int64_t>(left, kResidentMaxGens))
+        ops.push_back(Op{(int)std::min<int64_t>(left, kResidentMaxGens), -1});
       g = upto;
     } else if (upto > g) {
       for (int t : single_board_passes(upto - g, c.T)) ops.push_back(Op{t, -1});

@@ -74,6 +74,15 @@ def test_in_place_population_and_host_api():
     assert np.array_equal(gol.step(b2, 500), oracle.life(b2, 500))
 
 
+def test_runs_longer_than_one_launch():
+    """A run of more than 65536 generations is split into several launches."""
+    R, C, G = 8, 40, 65536 * 2 + 7
+    b = rand_bytes(4434, 0, R, C, 0.5)
+    say(f"resident R={R} C={C} G={G}")
+    got = from_dev(gol.step_packed(to_dev(oracle.pack(b)), R, C, G, config=RES))
+    assert np.array_equal(got, expect_words(b, G))
+
+
 def test_resident_rejects_a_board_too_large():
     import torch
     d = torch.zeros((257, 16), dtype=torch.int64, device="cuda")
