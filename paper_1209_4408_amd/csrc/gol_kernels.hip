@@ -27,6 +27,13 @@
 // outside the strip; wrong bits move inward one column per generation, so
 // after T <= 32 generations the halo dwords absorb them and every inner lane
 // is exact.  Likewise the T extra rows above and below the band.
+//
+// Besides the torus pass: the same pass on a bounded board (cells beyond the
+// edges dead at every generation) and on a strip of a larger torus whose halo
+// rows come from two other buffers (both selected by the gather mode);
+// batched passes over many boards from tables; small boards resident in one
+// workgroup's LDS for a whole run (k_board_lds); the live-cell count
+// (k_population); pack / unpack of byte boards.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -112,6 +119,8 @@ struct Lane {
   //   C < 64 (narrow): a, b = dwords 0 and 1 hold the whole row; it is
   //     repeated up a 64-bit word and the window read from bit q, which sh
   //     holds (and n1 holds C).
+  // Bounded boards read the lane's own dword (doff) and m1 keeps the bits
+  // that are cells of the board (0 for a lane beyond either edge).
   int32_t ia, ib;
   uint32_t sh, n1, m1;
   bool narrow;
