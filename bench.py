@@ -65,6 +65,16 @@ def cpu_threads() -> int:
     return os.cpu_count() or 1
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(rows, cols, p, seed, budget_s=12.0):
     """The oracle (plain C, row decomposition over OpenMP threads) on a bounded
     number of generations of the same board; cell-updates/s."""
@@ -79,10 +89,15 @@ def cpu_baseline(rows, cols, p, seed, budget_s=12.0):
     t0 = time.perf_counter()
     oracle.life(cur, g, threads=threads)
     dt = time.perf_counter() - t0
+    # one generation on one thread (the oracle without the row decomposition)
+    t0 = time.perf_counter()
+    oracle.life(cur, 1, threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": rows * cols * g / dt, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{g} generations of the {rows}x{cols} board (of the run's 1000), "
-                      f"{threads} OpenMP threads, byte-per-cell C oracle"}
+                      f"{threads} OpenMP threads, byte-per-cell C oracle",
+            "single_thread_value": rows * cols / dt1, "cpu_model": cpu_model()}
 
 
 def measured_traffic(record: str, cfg=None):
