@@ -15,7 +15,8 @@ board and Table 1's checks on the 16384^2 run), bounded (the 16384^2 board
 with dead surroundings instead of the torus), strip (one GPU's 8192 x 65536
 share of the 65536^2 board, halo rows from separate buffers), decomp (Table
 2's largest case on the GPU, with the CPU study of the row, column and 2-D
-decompositions as its baseline), copy (copy-kernel calibration of
+decompositions as its baseline), valu (the issue-rate probe of each VALU
+instruction kind the tile pass uses, against the ALU peak), copy (copy-kernel calibration of
 the traffic counters).
 """
 from __future__ import annotations
@@ -459,6 +460,18 @@ def copy_calibration(args):
                       "read_plus_write_GBps": 2 * R * C / 8 / dt / 1e9}), flush=True)
 
 
+def valu_workload(args):
+    """The VALU issue-rate probe: lane operations per second of each
+    instruction kind the tile pass issues, against the 78.6 T ops/s peak
+    (256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz) the ALU rooflines use."""
+    import paper_1209_4408_amd as gol
+    rates = {}
+    for k, name in enumerate(gol.VALU_KINDS):
+        best = max(gol.valu_rate(k) for _ in range(max(1, args.steps // 2)))
+        rates[name] = {"lane_ops_per_s": best, "frac_of_peak": best / VALU_PEAK_OPS}
+    print(json.dumps({"valu_probe": rates, "peak_lane_ops_per_s": VALU_PEAK_OPS}), flush=True)
+
+
 def population_workload(args):
     """Population (live cells, the paper's Table 1 quantity): the counting
     kernel alone on the 65536^2 board (HBM-bound: it reads the board once),
@@ -774,7 +787,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2",
                     choices=["c1", "c2", "c3", "c4", "c5", "copy", "pop", "bounded",
-                             "strip", "decomp"])
+                             "strip", "decomp", "valu"])
     ap.add_argument("--requests", type=int, default=4096)
     ap.add_argument("--rate", type=float, default=2700.0,
                     help="Poisson arrival rate; requests average 1.08e10 cell-updates, so "
@@ -849,6 +862,9 @@ def main():
         return
     elif args.workload == "decomp":
         decomp_workload(args)
+        return
+    elif args.workload == "valu":
+        valu_workload(args)
         return
     ms = res["wall_s"] / args.steps * 1e3
     line = {

@@ -57,6 +57,18 @@ int gol_debug_serve_create_host(const gol_serve_config* cfg, int64_t fail_at_chu
  * not a host-executor server). */
 int64_t gol_debug_serve_host_peak_bytes(const gol_server* srv);
 
+/*
+ * VALU issue-rate probe: *lane_ops_per_second receives the lane-operation
+ * rate of one instruction kind on the current device -- 32768 waves, each
+ * thread running eight independent chains of 2048 applications, timed with
+ * HIP events over one launch after a warm-up launch.  kind: 0 v_xor_b32,
+ * 1 v_bitop3_b32 (three VGPR sources), 2 v_alignbit_b32, 3 v_mov_b32 with
+ * DPP, 4 v_add_u32 -- the instruction kinds of the tile pass, which price
+ * its ALU roofline.  Synchronous on stream; GOL_EINVAL for another kind or
+ * a null pointer.
+ */
+int gol_debug_valu_rate(int kind, void* stream, double* lane_ops_per_second);
+
 #ifdef __cplusplus
 }
 #endif

@@ -117,6 +117,7 @@ def lib():
             "gol_debug_serve_create_host": (c_int, [ctypes.POINTER(ServeConfig), i64,
                                                     ctypes.POINTER(vp)]),
             "gol_debug_serve_host_peak_bytes": (i64, [vp]),
+            "gol_debug_valu_rate": (c_int, [c_int, vp, ctypes.POINTER(ctypes.c_double)]),
             "gol_debug_plan_tables": (c_int, [vp, vp, vp, i64, c_int, c_int, vp, i64, vp, i64, vp,
                                               i64, vp, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -223,6 +224,17 @@ def strip_pass(d_strip, d_top, d_bottom, rows: int, cols: int, t: int, d_out=Non
     _check(lib().gol_strip_pass(_ptr(d_strip), _ptr(d_top), _ptr(d_bottom), rows, cols, int(t),
                                 _ptr(d_out), _stream_handle(stream), ctypes.byref(c)))
     return d_out
+
+
+VALU_KINDS = ("v_xor_b32", "v_bitop3_b32", "v_alignbit_b32", "v_mov_b32_dpp", "v_add_u32")
+
+
+def valu_rate(kind: int, stream=None) -> float:
+    """Lane operations per second of one VALU instruction kind (VALU_KINDS[kind])
+    on the current device, from the issue-rate probe (synchronous)."""
+    r = ctypes.c_double()
+    _check(lib().gol_debug_valu_rate(int(kind), _stream_handle(stream), ctypes.byref(r)))
+    return r.value
 
 
 def population(d_packed, rows: int, cols: int, stream=None) -> int:

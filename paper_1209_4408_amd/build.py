@@ -20,7 +20,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"-I{INCLUDE}", f"-I{CSRC}", "-Wall",
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 HOST_SOURCES = ["gol_capi.cpp", "gol_plan.cpp", "gol_serve.cpp", "gol_tune.cpp"]
-DEVICE_SOURCES = ["gol_kernels.hip"]
+DEVICE_SOURCES = ["gol_kernels.hip", "gol_probe.hip"]
 
 
 def _run(cmd: list[str]) -> None:

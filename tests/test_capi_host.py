@@ -246,3 +246,12 @@ def test_resident_layout_rejects_boards_beyond_its_lds_budget():
     c = gol.PassConfig(0, 0, 0, gol.LAYOUT_RESIDENT)
     rc = L.gol_step_packed_bounded(fake, 64, 64, 5, ctypes.c_void_p(0x100000), None, ctypes.byref(c))
     assert rc == -1 and b"band layout" in L.gol_last_error()
+
+
+def test_valu_probe_rejects_bad_kinds_before_any_device_work():
+    import ctypes as C
+    L = gol.lib()
+    r = C.c_double()
+    assert L.gol_debug_valu_rate(-1, None, C.byref(r)) == -1
+    assert L.gol_debug_valu_rate(5, None, C.byref(r)) == -1
+    assert L.gol_debug_valu_rate(0, None, None) == -1

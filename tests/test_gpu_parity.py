@@ -275,3 +275,15 @@ def test_config_errors():
         with pytest.raises(gol.GolError) as e:
             gol.step_packed(d, R, C, 5, config=cfg)
         assert e.value.code == -1, cfg
+
+
+def test_valu_probe_reports_a_rate_for_every_kind():
+    """The issue-rate probe behind the ALU roofline: every instruction kind
+    gives a finite positive rate, no kind above twice the 78.6 T lane-ops/s
+    peak (64 lanes per SIMD per clock would be), and bad kinds are refused."""
+    for k in range(len(gol.VALU_KINDS)):
+        r = gol.valu_rate(k)
+        say("valu probe", gol.VALU_KINDS[k], r)
+        assert 0 < r < 2 * 78.6432e12
+    with pytest.raises(gol.GolError):
+        gol.valu_rate(5)
