@@ -16,7 +16,8 @@ Contents:
   * ``torus_window``: a wrapped sub-board, for light-cone checks of large runs;
   * ``population_at``: live cells after chosen generation counts (Table 1);
   * ``life_decomp``: the C oracle with the paper's row, column or 2-D block
-    decomposition over OpenMP threads (Sections 2.1-2.2), for the CPU study.
+    decomposition over OpenMP threads (Sections 2.1-2.2), for the CPU study;
+  * ``python -m oracle``: the same from the command line on .npy boards.
 """
 from __future__ import annotations
 

@@ -27,3 +27,21 @@ def test_decomposition_rejects_bad_arguments():
         oracle.life_decomp(b, 1, 0, "rows")
     with pytest.raises(ValueError):
         oracle.life_decomp(b, -1, 2, "2d")
+
+
+def test_command_line(tmp_path):
+    """python -m oracle: the same board as the library call, and the population
+    at the listed generations."""
+    import subprocess
+    import sys
+    b = seeded_inputs.board_bytes(561, 0, 30, 45, 0.4)
+    src, dst = tmp_path / "in.npy", tmp_path / "out.npy"
+    np.save(src, b)
+    r = subprocess.run([sys.executable, "-m", "oracle", str(src), "17", str(dst), "--threads", "3",
+                        "--decomposition", "2d", "--population", "0,5,17"],
+                       capture_output=True, text=True, check=True,
+                       cwd=str(__import__("pathlib").Path(oracle.__file__).parent.parent))
+    assert np.array_equal(np.load(dst), oracle.life(b, 17))
+    want = oracle.population_at(b, [0, 5, 17])
+    assert r.stdout.split() == [w for g, n in zip([0, 5, 17], want)
+                                for w in ("generation", f"{g}:", "population", str(n))]
