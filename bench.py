@@ -135,14 +135,34 @@ def with_full_adder_frac(roofline):
     return roofline
 
 
+_MIX_CEILING = None
+
+
+def measured_mix_ceiling():
+    """Cell-updates/s the chip allows for the tile pass's instruction mix at the
+    issue rates the VALU probe measures now: per 32 cells and generation a
+    pipeline stage issues 10 full-rate ops (v_bitop3 / v_and) and 4 half-rate
+    ones (2 DPP moves, 2 v_alignbit)."""
+    global _MIX_CEILING
+    if _MIX_CEILING is None:
+        import paper_1209_4408_amd as gol
+        full = gol.valu_rate(1)                         # v_bitop3_b32
+        half = 0.5 * (gol.valu_rate(2) + gol.valu_rate(3))  # v_alignbit_b32, DPP move
+        _MIX_CEILING = 32.0 / (10.0 / full + 4.0 / half)
+    return _MIX_CEILING
+
+
 def roofline_alu(cells, cfg, avg_launch_s):
     ops = OPS_PER_CELL_UPDATE * cells * cfg["t_block"]
     achieved = ops / avg_launch_s / 1e12
     peak = VALU_PEAK_OPS / 1e12
+    ceiling = measured_mix_ceiling()
+    rate = cells * cfg["t_block"] / avg_launch_s
     return with_full_adder_frac({
         "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
         "frac": achieved / peak, "traffic": None, "kernel": kernel_name(cfg),
-        "avg_launch_us": avg_launch_s * 1e6, "ops_per_launch": ops})
+        "avg_launch_us": avg_launch_s * 1e6, "ops_per_launch": ops,
+        "measured_mix_ceiling": {"cell_updates_per_s": ceiling, "frac": rate / ceiling}})
 
 
 def roofline_hbm(cells, avg_launch_s):
