@@ -1,23 +1,28 @@
 """Benchmark of the Life step library on one MI355X.
 
-Default workload (one "step" = the whole hot path over one input): a
-16384 x 16384 toroidal board, bit-packed, i.i.d. Bernoulli(0.3) cells from seed
-1209, advanced 1000 generations by gol_step_packed.  Prints one JSON line with
-cell-updates/s, the roofline of the dominant kernel and the CPU oracle timed
-on a bounded sample of the same workload.
+Default run (no --workload): every configuration of the metric in one process,
+one JSON line.  Its headline `value` is the HBM-scale single board: a 65536 x
+65536 toroidal board, bit-packed, i.i.d. Bernoulli(0.5) cells from seed 1209,
+advanced 200 generations by gol_step_packed in temporal-blocked passes, with
+the one-generation-per-launch kernel timed beside it.  Blocks of the same line
+carry the other configurations, each with its own timed region, roofline and
+CPU oracle baseline:
+  c2  16384 x 16384, Bernoulli(0.3), 1000 generations (plain single board);
+  c4  4096 boards of uneven sizes and generation counts in one batched
+      schedule, against the plain path (one gol_step_packed per board);
+  c5  an open-loop Poisson request stream through the continuous-batching
+      server (throughput, p50 / p99 latency), against a one-request-at-a-time
+      server on the same trace;
+  c1  a 256 x 256 byte board, 100 generations, through the host API.
+A "step" of a block is one pass of its whole workload: one board run (c3, c2),
+one schedule over all 4096 boards (c4), one stream of requests (c5).
 
-Other workloads (--workload): c1 (256^2 byte board, 100 generations, host
-API), c3 (65536^2, 200 generations, temporal-blocked vs one generation per
-launch), c4 (4096 boards in one batched schedule vs one launch sequence per
-board), c5 (Poisson request stream through the continuous-batching server vs
-a one-at-a-time server), pop (population counting: the kernel on the 65536^2
-board and Table 1's checks on the 16384^2 run), bounded (the 16384^2 board
-with dead surroundings instead of the torus), strip (one GPU's 8192 x 65536
-share of the 65536^2 board, halo rows from separate buffers), decomp (Table
-2's largest case on the GPU, with the CPU study of the row, column and 2-D
-decompositions as its baseline), valu (the issue-rate probe of each VALU
-instruction kind the tile pass uses, against the ALU peak), copy (copy-kernel calibration of
-the traffic counters).
+Other workloads (--workload) run one configuration alone (c1 ... c5) or a
+side study: pop (population counting), bounded (dead surroundings instead of
+the torus), strip (one GPU's 8192 x 65536 share of the 65536^2 board), decomp
+(Table 2's largest case, with the CPU study of the three decompositions), valu
+(the issue-rate probe of each VALU instruction kind the tile pass uses), copy
+(copy-kernel calibration of the traffic counters).
 """
 from __future__ import annotations
 
@@ -36,21 +41,21 @@ sys.path.insert(0, ROOT)
 # = 78.6 T ops/s, the published 157.3 TFLOP/s FP32 vector figure counted as
 # one op per FMA (integer and bitwise ops issue at the same lane rate).
 VALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9
-# Generations per pass of the batched and served schedules (the library's
-# default, passed explicitly so the reported configuration is the one run).
-BATCH_T = 16
 HBM_PEAK_BYTES = 8.0e12
-# Algorithmic integer ops per cell-update of the bit-sliced step: per 32-cell
-# word and generation 2 funnel shifts + 2 (horizontal 3-sum) + 4 (vertical
-# combine) + 4 (rule) = 12 ops.
-OPS_PER_CELL_UPDATE = 12.0 / 32.0
-# The same step priced as the textbook bit-sliced full-adder network without
-# three-input logic ops (24 ops per 32 cells); the kernel issues the 12-op
-# form, so `frac` uses OPS_PER_CELL_UPDATE and this count is reported beside it.
-FULL_ADDER_OPS_PER_CELL_UPDATE = 24.0 / 32.0
+# Algorithmic integer ops per cell-update: the bit-sliced full-adder network
+# written with two-input logic ops, 24 ops per 32-cell word and generation.
+# This is the count the ALU roofline is priced at (`frac`).
+OPS_PER_CELL_UPDATE = 24.0 / 32.0
+# The same network as the kernels issue it with gfx950's three-input v_bitop3:
+# 2 funnel shifts + 2 (horizontal 3-sum) + 4 (vertical combine) + 4 (rule)
+# = 12 ops per 32 cells; reported beside `frac`.
+ISSUED_OPS_PER_CELL_UPDATE = 12.0 / 32.0
 # Algorithmic HBM bytes per cell-update of a one-generation pass: read + write
 # one bit.
 BYTES_PER_CELL_UPDATE_T1 = 2.0 / 8.0
+# Generations per pass of the batched and served schedules (the library's
+# default, passed explicitly so the reported configuration is the one run).
+BATCH_T = 16
 
 SEED = 1209
 
@@ -76,9 +81,23 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(rows, cols, p, seed, budget_s=12.0):
+def _median_rate(fn, work, reps=3):
+    """Median over `reps` timed calls of fn() of work / seconds."""
+    rates = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        rates.append(work / (time.perf_counter() - t0))
+    return float(np.median(rates)), rates
+
+
+# ---------------------------------------------------------------------------
+# CPU oracle baselines (bounded samples of each workload)
+# ---------------------------------------------------------------------------
+def cpu_baseline_board(rows, cols, p, seed, total_gens, budget_s=15.0):
     """The oracle (plain C, row decomposition over OpenMP threads) on a bounded
-    number of generations of the same board; cell-updates/s."""
+    number of generations of the workload's own board: median of three timed
+    samples; the oracle's single-thread rate beside it."""
     import oracle
     import seeded_inputs
     threads = cpu_threads()
@@ -86,19 +105,101 @@ def cpu_baseline(rows, cols, p, seed, budget_s=12.0):
     t0 = time.perf_counter()
     cur = oracle.life(b, 1, threads=threads)
     one = time.perf_counter() - t0
-    g = max(1, min(1000, int(budget_s / max(one, 1e-6))))
+    g = int(max(1, min(total_gens, budget_s / 3.0 / max(one, 1e-6))))
+    value, rates = _median_rate(lambda: oracle.life(cur, g, threads=threads), rows * cols * g)
+    g1 = int(max(1, min(total_gens, 2.0 / max(one * threads, 1e-6))))
+    single, _ = _median_rate(lambda: oracle.life(cur, g1, threads=1), rows * cols * g1, reps=1)
+    return {"value": value, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{g} of the run's {total_gens} generations of the {rows}x{cols} board, "
+                      f"median of 3 timings, {threads} OpenMP threads (row decomposition), "
+                      f"byte-per-cell C oracle",
+            "rates": rates, "single_thread_value": single,
+            "single_thread_sample": f"{g1} generations, 1 thread", "cpu_model": cpu_model()}
+
+
+def cpu_baseline_boards(specs, seed, budget_s=12.0, what="boards"):
+    """The oracle over a sample of a mix's boards, each run for its full
+    generation count: every k-th board (k chosen so the sample's work fits the
+    budget at the oracle's rate on one probe board), rate = sampled
+    cell-updates / oracle seconds summed over the sample."""
+    import oracle
+    import seeded_inputs
+    threads = cpu_threads()
+    work = np.array([s.rows * s.cols * s.generations for s in specs], dtype=np.float64)
+    probe = specs[int(np.argsort(work)[len(specs) // 2])]
+    b = seeded_inputs.board_bytes(seed, probe.board_id, probe.rows, probe.cols, probe.p)
+    g = max(1, min(probe.generations, 50))
     t0 = time.perf_counter()
-    oracle.life(cur, g, threads=threads)
-    dt = time.perf_counter() - t0
-    # one generation on one thread (the oracle without the row decomposition)
-    t0 = time.perf_counter()
-    oracle.life(cur, 1, threads=1)
-    dt1 = time.perf_counter() - t0
-    return {"value": rows * cols * g / dt, "unit": "cell-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{g} generations of the {rows}x{cols} board (of the run's 1000), "
-                      f"{threads} OpenMP threads, byte-per-cell C oracle",
-            "single_thread_value": rows * cols / dt1, "cpu_model": cpu_model()}
+    oracle.life(b, g, threads=threads)
+    rate = probe.rows * probe.cols * g / max(time.perf_counter() - t0, 1e-6)
+    k = max(1, int(np.ceil(work.sum() / rate / budget_s)))
+    sample = specs[::k]
+    done, secs = 0.0, 0.0
+    for s in sample:
+        b = seeded_inputs.board_bytes(seed, s.board_id, s.rows, s.cols, s.p)
+        t0 = time.perf_counter()
+        oracle.life(b, s.generations, threads=threads)
+        secs += time.perf_counter() - t0
+        done += s.rows * s.cols * s.generations
+        if secs > 2.5 * budget_s:
+            break
+    return {"value": done / secs, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {k}-th of the {len(specs)} {what} run whole by the oracle "
+                      f"({done:.3e} of {work.sum():.3e} cell-updates, {secs:.1f} s), summed "
+                      f"over boards, {threads} OpenMP threads",
+            "cpu_model": cpu_model()}
+
+
+# ---------------------------------------------------------------------------
+# Rooflines
+# ---------------------------------------------------------------------------
+def alu_roofline(cell_updates_per_launch, avg_launch_s, kernel, **extra):
+    """ALU roofline record of a temporal-blocked pass: algorithmic ops (24 per
+    32 cells and generation) per launch / average launch duration, against the
+    78.6 T ops/s VALU peak; the issued 12-op count beside it."""
+    ops = OPS_PER_CELL_UPDATE * cell_updates_per_launch
+    achieved = ops / avg_launch_s / 1e12
+    peak = VALU_PEAK_OPS / 1e12
+    issued = ISSUED_OPS_PER_CELL_UPDATE * cell_updates_per_launch / avg_launch_s / 1e12
+    rec = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+           "frac": achieved / peak, "traffic": None, "kernel": kernel,
+           "avg_launch_us": avg_launch_s * 1e6, "ops_per_launch": ops,
+           "ops_per_cell_update": OPS_PER_CELL_UPDATE,
+           "at_issued_12_ops_per_32_cells": {"achieved": issued, "frac": issued / peak}}
+    rec.update(extra)
+    return rec
+
+
+def hbm_roofline(cell_updates_per_launch, avg_launch_s, kernel):
+    by = BYTES_PER_CELL_UPDATE_T1 * cell_updates_per_launch
+    achieved = by / avg_launch_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
+            "frac": achieved / (HBM_PEAK_BYTES / 1e9), "traffic": None, "kernel": kernel,
+            "avg_launch_us": avg_launch_s * 1e6, "bytes_per_launch": by}
+
+
+_MIX_CEILING = None
+
+
+def measured_mix_ceiling():
+    """Cell-updates/s the chip allows for the tile pass's instruction mix at the
+    issue rates the VALU probe measures now: per 32 cells and generation a
+    pipeline stage issues 10 full-rate ops (v_bitop3 / v_and) and 4 half-rate
+    ones (2 DPP moves, 2 v_alignbit)."""
+    global _MIX_CEILING
+    if _MIX_CEILING is None:
+        import paper_1209_4408_amd as gol
+        full = gol.valu_rate(1)                         # v_bitop3_b32
+        half = 0.5 * (gol.valu_rate(2) + gol.valu_rate(3))  # v_alignbit_b32, DPP move
+        _MIX_CEILING = 32.0 / (10.0 / full + 4.0 / half)
+    return _MIX_CEILING
+
+
+def with_mix_ceiling(rec, cell_updates_per_s):
+    ceiling = measured_mix_ceiling()
+    rec["measured_mix_ceiling"] = {"cell_updates_per_s": ceiling,
+                                   "frac": cell_updates_per_s / ceiling}
+    return rec
 
 
 def measured_traffic(record: str, cfg=None):
@@ -119,7 +220,7 @@ def measured_traffic(record: str, cfg=None):
     return rec["hbm_bytes_per_launch"]
 
 
-def kernel_name(cfg, cols=16384):
+def kernel_name(cfg, cols):
     """The tile-pass kernel a launch configuration runs on a torus of `cols`
     columns (gather 1: whole dwords, 0: rows that end inside a dword)."""
     T, pd = cfg["t_block"], cfg["prefetch"]
@@ -128,82 +229,30 @@ def kernel_name(cfg, cols=16384):
     return f"k_board_pass<{T}, {pd}, {1 if cols % 32 == 0 else 0}>"
 
 
-def with_full_adder_frac(roofline):
-    """An ALU roofline record plus its fraction at the full-adder op count."""
-    roofline["frac_at_24_ops_per_32_cells"] = (
-        roofline["frac"] * FULL_ADDER_OPS_PER_CELL_UPDATE / OPS_PER_CELL_UPDATE)
-    return roofline
-
-
-_MIX_CEILING = None
-
-
-def measured_mix_ceiling():
-    """Cell-updates/s the chip allows for the tile pass's instruction mix at the
-    issue rates the VALU probe measures now: per 32 cells and generation a
-    pipeline stage issues 10 full-rate ops (v_bitop3 / v_and) and 4 half-rate
-    ones (2 DPP moves, 2 v_alignbit)."""
-    global _MIX_CEILING
-    if _MIX_CEILING is None:
-        import paper_1209_4408_amd as gol
-        full = gol.valu_rate(1)                         # v_bitop3_b32
-        half = 0.5 * (gol.valu_rate(2) + gol.valu_rate(3))  # v_alignbit_b32, DPP move
-        _MIX_CEILING = 32.0 / (10.0 / full + 4.0 / half)
-    return _MIX_CEILING
-
-
-def roofline_alu(cells, cfg, avg_launch_s):
-    ops = OPS_PER_CELL_UPDATE * cells * cfg["t_block"]
-    achieved = ops / avg_launch_s / 1e12
-    peak = VALU_PEAK_OPS / 1e12
-    ceiling = measured_mix_ceiling()
-    rate = cells * cfg["t_block"] / avg_launch_s
-    return with_full_adder_frac({
-        "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-        "frac": achieved / peak, "traffic": None, "kernel": kernel_name(cfg),
-        "avg_launch_us": avg_launch_s * 1e6, "ops_per_launch": ops,
-        "measured_mix_ceiling": {"cell_updates_per_s": ceiling, "frac": rate / ceiling}})
-
-
-def roofline_hbm(cells, avg_launch_s):
-    by = BYTES_PER_CELL_UPDATE_T1 * cells
-    achieved = by / avg_launch_s / 1e9
-    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
-            "frac": achieved / (HBM_PEAK_BYTES / 1e9), "traffic": None,
-            "kernel": "k_board_pass<1, 3, 1>", "avg_launch_us": avg_launch_s * 1e6,
-            "bytes_per_launch": by}
-
-
-def time_packed(gol, torch, d_in, d_out, R, C, G, steps, warmup, T, config=None):
+# ---------------------------------------------------------------------------
+# Timing helpers (HIP events on the stream the kernels are launched on)
+# ---------------------------------------------------------------------------
+def timed_region(torch, fn, steps, warmup, stream=None):
+    """warmup untimed calls, then `steps` calls bracketed by synchronisations;
+    returns (wall seconds, device seconds between events on the stream)."""
+    st = stream or torch.cuda.current_stream()
     for _ in range(warmup):
-        gol.step_packed(d_in, R, C, G, d_out, t_block=T, config=config)
+        fn()
     torch.cuda.synchronize()
-    st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     e0.record(st)
     for _ in range(steps):
-        gol.step_packed(d_in, R, C, G, d_out, t_block=T, config=config)
+        fn()
     e1.record(st)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    dev = e0.elapsed_time(e1) / 1e3
-    return wall, dev
+    return time.perf_counter() - t0, e0.elapsed_time(e1) / 1e3
 
 
-def single_board(args, R, C, G, p, label):
-    import torch
-    import paper_1209_4408_amd as gol
-    import seeded_inputs
-    from paper_1209_4408_amd import build as _b  # noqa: F401
-    log(f"generating {R}x{C} board p={p}")
-    w = seeded_inputs.board_packed(SEED, 0, R, C, p)
-    d_in = torch.from_numpy(w.view(np.int64)).cuda()
-    del w
-    d_out = torch.empty_like(d_in)
-    torch.cuda.synchronize()
-    if args.config:
-        t, h, pd, lay = (int(v) for v in args.config.split(","))
+def resolve_config(gol, R, C, args, fixed):
+    """Launch configuration of a single-board block: explicit, or autotuned."""
+    if fixed:
+        t, h, pd, lay = (int(v) for v in fixed.split(","))
         cfg = {"t_block": t, "band_rows": h, "prefetch": pd, "layout": lay}
     elif args.t_block:
         cfg = {"t_block": args.t_block, "band_rows": 0, "prefetch": 0, "layout": 1}
@@ -212,33 +261,76 @@ def single_board(args, R, C, G, p, label):
     else:
         # one-off autotuning of the launch configuration for this size, before timing
         cfg = gol.tune_config(R, C)
-        log(f"autotuned: {cfg}")
+        log(f"autotuned {R}x{C}: {cfg}")
     if not cfg["prefetch"]:
         cfg["prefetch"] = {16: 12, 12: 9, 8: 9}.get(cfg["t_block"], 3)
-    args.tuned = cfg
+    return cfg
+
+
+def single_board(args, R, C, G, p, fixed_cfg="", compare_t1=False, cpu=True):
+    """One board of R x C cells, G generations, in the autotuned configuration.
+
+    Timed regions: (1) the whole run, `steps` times -> value; (2) the
+    dominant kernel alone: runs of G - G mod t_block generations, which are
+    whole t_block passes only -> its average launch duration; (3) optionally
+    the one-generation-per-launch kernel on the same board."""
+    import torch
+    import paper_1209_4408_amd as gol
+    import seeded_inputs
+    log(f"generating {R}x{C} board p={p}")
+    w = seeded_inputs.board_packed(SEED, 0, R, C, p)
+    d_in = torch.from_numpy(w.view(np.int64)).cuda()
+    del w
+    d_out = torch.empty_like(d_in)
+    torch.cuda.synchronize()
+    cfg = resolve_config(gol, R, C, args, fixed_cfg)
     T = cfg["t_block"]
-    log(f"timing {args.steps} steps after {args.warmup} warmup, {cfg}")
     run_cfg = cfg if cfg["band_rows"] else None
-    wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, args.steps, args.warmup,
-                            0 if run_cfg else T, config=run_cfg)
+    tb = 0 if run_cfg else T
+    log(f"timing {R}x{C}x{G}: {args.steps} steps after {args.warmup} warmup, {cfg}")
+    wall, dev = timed_region(torch, lambda: gol.step_packed(d_in, R, C, G, d_out, t_block=tb,
+                                                            config=run_cfg),
+                             args.steps, args.warmup)
     cells = R * C
     value = cells * G * args.steps / wall
-    # average duration of one T-generation pass: device time per generation x T
-    # (a run of G = 1000 at T = 12 also holds one 4-generation pass)
-    avg_launch = dev / (args.steps * G) * T
-    res = {"value": value, "wall_s": wall, "dev_s": dev,
-           "roofline": roofline_alu(cells, cfg, avg_launch) if T > 1 else roofline_hbm(cells,
-                                                                                         avg_launch)}
-    rec = f"traffic_{res['roofline']['kernel'].split('<')[0]}_{R}x{C}.json"
-    res["roofline"]["traffic"] = measured_traffic(rec, cfg)
-    extra = {}
-    if args.compare_t1:
-        wall1, dev1 = time_packed(gol, torch, d_in, d_out, R, C, G, max(1, args.steps // 2), 1, 1)
-        v1 = cells * G * max(1, args.steps // 2) / wall1
-        extra["t1"] = {"value": v1, "unit": "cell-updates/s",
-                       "roofline": roofline_hbm(cells, dev1 / (max(1, args.steps // 2) * G))}
-        extra["speedup_vs_t1"] = value / v1
-    return res, extra
+    blk = {"metric": "cell-updates/sec", "value": value, "unit": "cell-updates/s",
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "timed_s": wall, "device_s": dev, "dtype": "u32",
+           "config": {"workload": f"{R}x{C} torus, bit-packed, Bernoulli({p}), {G} generations",
+                      "rows": R, "cols": C, "generations": G, "p": p, "seed": SEED, **cfg,
+                      "layout": {1: "band", 2: "paired", 3: "resident"}.get(cfg["layout"])}}
+    if T > 1 and cfg["layout"] != 3:
+        g_main = (G // T) * T
+        passes = g_main // T
+        _, dev_k = timed_region(torch, lambda: gol.step_packed(d_in, R, C, g_main, d_out,
+                                                               t_block=tb, config=run_cfg),
+                                args.steps, 1)
+        avg = dev_k / (args.steps * passes)
+        roof = alu_roofline(cells * T, avg, kernel_name(cfg, C),
+                            launches_timed=args.steps * passes,
+                            timed_as=f"runs of {g_main} generations ({passes} passes of {T})")
+        roof = with_mix_ceiling(roof, cells * T / avg)
+        rec = f"traffic_{roof['kernel'].split('<')[0]}_{R}x{C}.json"
+        roof["traffic"] = measured_traffic(rec, cfg)
+        blk["roofline"] = roof
+    else:
+        blk["roofline"] = None
+    if compare_t1:
+        n1 = max(2, args.steps // 2)
+        log(f"timing {R}x{C}x{G} one generation per launch: {n1} steps")
+        wall1, dev1 = timed_region(torch, lambda: gol.step_packed(d_in, R, C, G, d_out,
+                                                                  t_block=1), n1, 1)
+        blk["t1"] = {"value": cells * G * n1 / wall1, "unit": "cell-updates/s", "steps": n1,
+                     "timed_s": wall1,
+                     "roofline": hbm_roofline(cells, dev1 / (n1 * G),
+                                              f"k_board_pass<1, 3, {1 if C % 32 == 0 else 0}>")}
+        blk["speedup_vs_t1"] = value / blk["t1"]["value"]
+    del d_in, d_out
+    torch.cuda.empty_cache()
+    if cpu and not args.no_cpu:
+        log(f"cpu baseline (oracle) on {R}x{C}")
+        blk["cpu_baseline"] = cpu_baseline_board(R, C, p, SEED, G)
+    return blk
 
 
 def board_set_device(specs, seed):
@@ -258,9 +350,10 @@ def board_set_device(specs, seed):
     return host, d_in, d_out, ins, outs
 
 
-def batched(args):
+def batched(args, cpu=True):
     """4096 boards of uneven sizes and generation counts: one batched schedule
-    (graph replay) against the plain path, one gol_step_packed per board."""
+    (graph replay) against the plain path, one gol_step_packed per board with
+    the library's default configuration, sequential on one stream."""
     import torch
     import paper_1209_4408_amd as gol
     import seeded_inputs
@@ -269,58 +362,49 @@ def batched(args):
     log(f"generating {len(specs)} boards, {work:.3e} cell-updates")
     _, d_in, d_out, ins, outs = board_set_device(specs, SEED)
     T = args.t_block or BATCH_T
-    args.tuned = {"t_block": T}
-    boards = [gol.BatchBoard(i, o, s.rows, s.cols, s.generations) for s, i, o in zip(specs, ins, outs)]
+    boards = [gol.BatchBoard(i, o, s.rows, s.cols, s.generations)
+              for s, i, o in zip(specs, ins, outs)]
     st = torch.cuda.Stream()
     plan = gol.Plan(boards, t_block=T)
     info = plan.info()
+    log(f"timing the batched schedule: {args.steps} steps after {args.warmup} warmup")
     with torch.cuda.stream(st):
-        for _ in range(args.warmup):
-            plan.run(st)
-        st.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        e0.record(st)
-        for _ in range(args.steps):
-            plan.run(st)
-        e1.record(st)
-        st.synchronize()
-        wall = time.perf_counter() - t0
-    dev = e0.elapsed_time(e1) / 1e3
-    value = work * args.steps / wall
+        wall, dev = timed_region(torch, lambda: plan.run(st), args.steps, args.warmup, st)
     plan.close()
-    levels = info["levels"]
-    res = {"value": value, "wall_s": wall, "dev_s": dev,
-           "roofline": roofline_alu_total(work, dev / args.steps, levels, T)}
-    if args.no_plain:
-        return res, {"plan": info}
-    # plain: one launch sequence per board, sequential on one stream
-    log("plain per-board loop")
-    with torch.cuda.stream(st):
-        for s, i, o in zip(specs, ins, outs):
-            gol.step_packed(i, s.rows, s.cols, s.generations, o, stream=st, t_block=T)
-        st.synchronize()
-        t0 = time.perf_counter()
-        for s, i, o in zip(specs, ins, outs):
-            gol.step_packed(i, s.rows, s.cols, s.generations, o, stream=st, t_block=T)
-        st.synchronize()
-        wall_plain = time.perf_counter() - t0
-    plain = work / wall_plain
-    extra = {"plain": {"value": plain, "unit": "cell-updates/s",
-                       "what": "one gol_step_packed per board, sequential, same stream"},
-             "speedup_vs_plain": value / plain, "plan": info}
-    return res, extra
+    value = work * args.steps / wall
+    per = dev / args.steps
+    roof = alu_roofline(work, per, f"k_batch_pass<{T}, *>", launches=info["levels"],
+                        note="algorithmic ops of the whole schedule over its device time "
+                             "(two streams overlap, so per-launch durations are not "
+                             "separable)")
+    blk = {"metric": "cell-updates/sec", "value": value, "unit": "cell-updates/s",
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "timed_s": wall, "device_s": dev, "dtype": "u32",
+           "config": {"workload": f"{len(specs)} boards, rows/cols log-uniform [64, 2048], "
+                                  "p U(0.1, 0.6), generations U{10..1000}, one batched "
+                                  "schedule", "boards": len(specs), "seed": SEED,
+                      "t_block": T, "cell_updates": work},
+           "roofline": roof, "plan": info}
+    if not args.no_plain:
+        log("plain per-board loop (library default configuration)")
+        plain_steps = 1
 
-
-def roofline_alu_total(work, dev_s, launches, T):
-    ops = OPS_PER_CELL_UPDATE * work
-    achieved = ops / dev_s / 1e12
-    peak = VALU_PEAK_OPS / 1e12
-    return with_full_adder_frac({
-        "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-        "frac": achieved / peak, "traffic": None, "kernel": f"k_batch_pass<{T}>",
-        "avg_launch_us": dev_s / max(1, launches) * 1e6, "launches": launches,
-        "ops_per_schedule": ops})
+        def plain():
+            for s, i, o in zip(specs, ins, outs):
+                gol.step_packed(i, s.rows, s.cols, s.generations, o, stream=st)
+        with torch.cuda.stream(st):
+            wall_p, _ = timed_region(torch, plain, plain_steps, 1, st)
+        blk["plain"] = {"value": work * plain_steps / wall_p, "unit": "cell-updates/s",
+                        "steps": plain_steps, "timed_s": wall_p,
+                        "what": "one gol_step_packed per board (library default "
+                                "configuration), sequential, same stream"}
+        blk["speedup_vs_plain"] = value / blk["plain"]["value"]
+    del d_in, d_out, ins, outs
+    torch.cuda.empty_cache()
+    if cpu and not args.no_cpu:
+        log("cpu baseline (oracle) on a sample of the boards")
+        blk["cpu_baseline"] = cpu_baseline_boards(specs, SEED, what="boards")
+    return blk
 
 
 def host_api(args):
@@ -336,22 +420,34 @@ def host_api(args):
     for _ in range(max(3, args.warmup)):
         gol.step(b, G, out=out)
     lat = []
-    for _ in range(max(20, args.steps)):
+    n = max(20, args.steps)
+    for _ in range(n):
         t0 = time.perf_counter()
         gol.step(b, G, out=out)
         lat.append(time.perf_counter() - t0)
     lat = np.array(lat)
-    import oracle
-    w = oracle.pack(b)
+    w = seeded_inputs.board_packed(SEED, 0, R, C, 0.5)
     d_in = torch.from_numpy(w.view(np.int64)).cuda()
     d_out = torch.empty_like(d_in)
-    wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, 20, 3, args.t_block)
-    res = {"value": R * C * G / float(np.median(lat)), "wall_s": float(lat.sum()),
-           "dev_s": dev, "roofline": None}
-    extra = {"host_api_us": {"p50": float(np.median(lat) * 1e6),
-                             "p99": float(np.percentile(lat, 99, method="nearest") * 1e6)},
-             "device_us_per_call": dev / 20 * 1e6}
-    return res, extra, len(lat)
+    _, dev = timed_region(torch, lambda: gol.step_packed(d_in, R, C, G, d_out), 20, 3)
+    blk = {"metric": "cell-updates/sec", "value": R * C * G / float(np.median(lat)),
+           "unit": "cell-updates/s", "steps": n, "timed_s": float(lat.sum()),
+           "config": {"workload": "256x256 torus, uint8 cells, Bernoulli(0.5), 100 "
+                                  "generations, host API (PCIe included)", "rows": R,
+                      "cols": C, "generations": G, "p": 0.5, "seed": SEED},
+           "roofline": None,
+           "host_api_us": {"p50": float(np.median(lat) * 1e6),
+                           "p99": float(np.percentile(lat, 99, method="nearest") * 1e6)},
+           "device_us_per_call": dev / 20 * 1e6}
+    if not args.no_cpu:
+        import oracle
+        threads = cpu_threads()
+        single, rates = _median_rate(lambda: oracle.life(b, G, threads=1), R * C * G)
+        blk["cpu_baseline"] = {"value": single, "unit": "cell-updates/s", "cores": 1,
+                               "kind": "oracle", "sample": "the whole run, median of 3, one "
+                               "thread (a board this small does not gain from threads)",
+                               "cpu_model": cpu_model(), "threads_available": threads}
+    return blk
 
 
 def wait_until(t0, at):
@@ -371,7 +467,7 @@ def nearest_rank(xs, q):
     return xs[k - 1]
 
 
-def served(args):
+def served(args, rate, cpu=True, plain=True):
     """Open-loop Poisson stream through the continuous-batching server, against
     a one-request-at-a-time server (gol_step_packed per request) on the same
     trace.  Latency = completion - scheduled arrival."""
@@ -379,57 +475,62 @@ def served(args):
     import torch
     import paper_1209_4408_amd as gol
     import seeded_inputs
-    specs = seeded_inputs.serve_specs(SEED, n=args.requests, rate_per_s=args.rate)
-    log(f"generating {len(specs)} request boards")
+    specs = seeded_inputs.serve_specs(SEED, n=args.requests, rate_per_s=rate)
+    log(f"generating {len(specs)} request boards (rate {rate:.0f}/s)")
     payloads = [seeded_inputs.board_packed(SEED, s.board_id, s.rows, s.cols, s.p) for s in specs]
     work = float(sum(s.rows * s.cols * s.generations for s in specs))
     results = [None] * len(specs)
+    T = args.t_block or BATCH_T
 
-    def run_server():
-        srv = gol.Server(hbm_budget_bytes=64 << 30, chunk_generations=args.chunk,
-                         t_block=args.t_block or BATCH_T)
-        args.tuned = {"t_block": args.t_block or BATCH_T}
-        # warm the pools: one small request
-        w = payloads[0]
-        t = srv.submit(w, specs[0].rows, specs[0].cols, 1)
-        srv.wait(t, np.zeros_like(w))
-        done = [None] * len(specs)
-        tickets = [None] * len(specs)
-        ready = threading.Semaphore(0)
+    srv = gol.Server(hbm_budget_bytes=64 << 30, chunk_generations=args.chunk, t_block=T)
+    # warm the pools: one small request
+    w = payloads[0]
+    srv.wait(srv.submit(w, specs[0].rows, specs[0].cols, 1), np.zeros_like(w))
+    done = [None] * len(specs)
+    tickets = [None] * len(specs)
+    ready = threading.Semaphore(0)
 
-        def waiter():
-            for i in range(len(specs)):
-                ready.acquire()
-                out = np.empty_like(payloads[i])
-                info = srv.wait(tickets[i], out)
-                done[i] = info.done_s
-                results[i] = out
-
-        th = threading.Thread(target=waiter)
-        th.start()
-        base = srv.now()
-        t0 = time.perf_counter()
-        for i, s in enumerate(specs):
-            wait_until(t0, s.arrival_s)
-            tickets[i] = srv.submit(payloads[i], s.rows, s.cols, s.generations)
-            ready.release()
-        th.join()
-        stats = srv.stats()
-        srv.close()
-        arr = [base + s.arrival_s for s in specs]
-        lat = [d - a for d, a in zip(done, arr)]
-        span = max(done) - arr[0]
-        return work / span, lat, span, stats
+    def waiter():
+        for i in range(len(specs)):
+            ready.acquire()
+            out = np.empty_like(payloads[i])
+            info = srv.wait(tickets[i], out)
+            done[i] = info.done_s
+            results[i] = out
 
     log("continuous-batching server")
-    thr, lat, span, stats = run_server()
-    out = {"value": thr, "wall_s": span, "dev_s": None, "roofline": None}
-    extra = {"latency_s": {"p50": nearest_rank(lat, 50), "p99": nearest_rank(lat, 99),
-                           "max": max(lat)},
-             "requests": len(specs), "rate_per_s": args.rate, "chunk_generations": args.chunk,
-             "hbm_budget_bytes": 64 << 30, "work_cell_updates": work, "server": stats}
-    # plain: FIFO, one request at a time, same arrival times
-    n_plain = min(len(specs), args.plain_requests)
+    th = threading.Thread(target=waiter)
+    th.start()
+    base = srv.now()
+    t0 = time.perf_counter()
+    for i, s in enumerate(specs):
+        wait_until(t0, s.arrival_s)
+        tickets[i] = srv.submit(payloads[i], s.rows, s.cols, s.generations)
+        ready.release()
+    th.join()
+    stats = srv.stats()
+    srv.close()
+    arr = [base + s.arrival_s for s in specs]
+    lat = [d - a for d, a in zip(done, arr)]
+    span = max(done) - arr[0]
+    thr = work / span
+    blk = {"metric": "cell-updates/sec", "value": thr, "unit": "cell-updates/s", "steps": 1,
+           "timed_s": span, "dtype": "u32",
+           "config": {"workload": f"{len(specs)} requests, Poisson {rate:.0f}/s, sides "
+                                  "log-uniform [32, 8192], p U(0.05, 0.7), generations "
+                                  "U{1..10000}, 64 GiB budget", "requests": len(specs),
+                      "rate_per_s": rate, "chunk_generations": args.chunk, "t_block": T,
+                      "hbm_budget_bytes": 64 << 30, "seed": SEED, "cell_updates": work},
+           "latency_s": {"p50": nearest_rank(lat, 50), "p99": nearest_rank(lat, 99),
+                         "max": max(lat)},
+           "offered_cell_updates_per_s": work / (specs[-1].arrival_s - specs[0].arrival_s),
+           "server": stats, "roofline": None}
+    if stats.get("device_busy_s"):
+        blk["roofline"] = alu_roofline(stats["cell_updates"], stats["device_busy_s"],
+                                       f"k_batch_pass<{T}, *>", launches=stats["launches"],
+                                       note="algorithmic ops of every chunk over the chunks' "
+                                            "device time (first to last launch of each)")
+    n_plain = min(len(specs), args.plain_requests) if plain else 0
     if n_plain > 0:
         log(f"plain one-at-a-time server on the first {n_plain} requests")
         st = torch.cuda.current_stream()
@@ -448,14 +549,80 @@ def served(args):
                 mism += 1
         span_p = time.perf_counter() - t0 - specs[0].arrival_s
         work_p = float(sum(s.rows * s.cols * s.generations for s in specs[:n_plain]))
-        extra["plain"] = {"value": work_p / span_p, "unit": "cell-updates/s",
-                          "requests": n_plain,
-                          "latency_s": {"p50": nearest_rank(lat_p, 50),
-                                        "p99": nearest_rank(lat_p, 99)},
-                          "what": "FIFO, one request at a time, gol_step_packed per request"}
-        extra["served_equals_alone"] = (mism == 0)
-        extra["speedup_vs_plain"] = thr / extra["plain"]["value"]
-    return out, extra
+        blk["plain"] = {"value": work_p / span_p, "unit": "cell-updates/s", "requests": n_plain,
+                        "timed_s": span_p,
+                        "latency_s": {"p50": nearest_rank(lat_p, 50),
+                                      "p99": nearest_rank(lat_p, 99)},
+                        "what": "FIFO, one request at a time, gol_step_packed per request"}
+        blk["served_equals_alone"] = (mism == 0)
+        blk["speedup_vs_plain"] = thr / blk["plain"]["value"]
+    if cpu and not args.no_cpu:
+        log("cpu baseline (oracle) on a sample of the requests")
+        blk["cpu_baseline"] = cpu_baseline_boards(specs, SEED, what="requests")
+    return blk
+
+
+def default_line(args):
+    """Every configuration of the metric; the headline is the 65536^2 board."""
+    import torch
+    blocks = {}
+    log("== c3: 65536^2 x 200")
+    c3 = single_board(args, 65536, 65536, 200, 0.5, args.config_c3, compare_t1=True)
+    log("== c2: 16384^2 x 1000")
+    blocks["c2"] = single_board(args, 16384, 16384, 1000, 0.3, args.config_c2)
+    log("== c4: 4096 boards")
+    blocks["c4"] = batched(args)
+    # the served stream's arrival rate: 0.7 of the batched capacity just measured,
+    # in requests per second of the stream's own mean work
+    import seeded_inputs
+    sp = seeded_inputs.serve_specs(SEED, n=args.requests, rate_per_s=1.0)
+    mean_work = float(np.mean([s.rows * s.cols * s.generations for s in sp]))
+    rate = args.rate or 0.7 * blocks["c4"]["value"] / mean_work
+    log(f"== c5: Poisson stream at {rate:.0f} requests/s")
+    blocks["c5"] = served(args, rate)
+    blocks["c5"]["rate_rule"] = ("0.7 x the batched block's cell-updates/s / the stream's mean "
+                                 "work per request" if not args.rate else "--rate")
+    log("== c1: host API")
+    blocks["c1"] = host_api(args)
+    torch.cuda.synchronize()
+    line = {
+        "metric": "cell-updates/sec",
+        "value": c3["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": c3["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {**c3["config"], "parallelism": "single GPU"},
+        "roofline": c3["roofline"],
+        "timed_s": c3["timed_s"],
+        "t1": c3.get("t1"),
+        "speedup_vs_t1": c3.get("speedup_vs_t1"),
+        "blocks": blocks,
+        "batched_over_plain": blocks["c4"].get("speedup_vs_plain"),
+        "served_over_plain": blocks["c5"].get("speedup_vs_plain"),
+    }
+    if "cpu_baseline" in c3:
+        line["cpu_baseline"] = c3["cpu_baseline"]
+    return line
+
+
+def single_line(args, blk, parallelism="single GPU"):
+    """A one-configuration JSON line from a block."""
+    line = {"metric": "cell-updates/sec", "value": blk["value"], "unit": "cell-updates/s",
+            "n_gpus": 1, "steps": blk["steps"], "warmup": blk.get("warmup", args.warmup),
+            "ms_per_step": blk["timed_s"] / blk["steps"] * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+            "config": {**blk["config"], "parallelism": parallelism}}
+    for k, v in blk.items():
+        if k not in line and k not in ("metric", "unit"):
+            line[k] = v
+    return line
 
 
 def copy_calibration(args):
@@ -591,7 +758,6 @@ def bounded_workload(args):
     wall, dev = timed(lambda: gol.step_packed_bounded(d_in, R, C, G, d_out, config=cfg))
     wall_t, dev_t = timed(lambda: gol.step_packed(d_in, R, C, G, d_out, config=cfg))
     avg_launch = dev / (args.steps * G) * T
-    ops = OPS_PER_CELL_UPDATE * R * C * T
     value = R * C * G * args.steps / wall
     line = {"metric": "cell-updates/sec", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
@@ -601,12 +767,7 @@ def bounded_workload(args):
                                    "Bernoulli(0.3), 1000 generations", "rows": R, "cols": C,
                        "generations": G, "p": p, "seed": SEED, **cfg, "layout": "band",
                        "parallelism": "single GPU"},
-            "roofline": with_full_adder_frac({
-                "bound": "alu", "achieved": ops / avg_launch / 1e12,
-                "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
-                "frac": ops / avg_launch / VALU_PEAK_OPS, "traffic": None,
-                "kernel": f"k_board_pass<{T}, {pd}, 2>",
-                "avg_launch_us": avg_launch * 1e6, "ops_per_launch": ops}),
+            "roofline": alu_roofline(R * C * T, avg_launch, f"k_board_pass<{T}, {pd}, 2>"),
             "torus_same_config": {"value": R * C * G * args.steps / wall_t,
                                   "unit": "cell-updates/s"}}
     print(json.dumps(line), flush=True)
@@ -672,7 +833,6 @@ def strip_workload(args):
     wall_big, _ = timed(lambda: gol.step_packed(big, R2, C, G, big_out, config=cfg))
     del big, big_out
     avg_launch = dev_k / (args.steps * len(passes))
-    ops = OPS_PER_CELL_UPDATE * rows * C * G / len(passes)  # average per launch
     value = rows * C * G * args.steps / wall
     line = {"metric": "cell-updates/sec", "value": value, "unit": "cell-updates/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
@@ -683,12 +843,9 @@ def strip_workload(args):
                                    "200 generations", "rows": rows, "cols": C, "generations": G,
                        "p": p, "seed": SEED, "passes": passes, "layout": "band",
                        "parallelism": "single GPU (one GPU's share)"},
-            "roofline": with_full_adder_frac({
-                "bound": "alu", "achieved": ops / avg_launch / 1e12,
-                "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
-                "frac": ops / avg_launch / VALU_PEAK_OPS, "traffic": None,
-                "kernel": f"k_board_pass<{t}, {pd}, 5>",
-                "avg_launch_us": avg_launch * 1e6, "ops_per_launch": ops}),
+            # cell-updates per launch: the average over the passes of the run
+            "roofline": alu_roofline(rows * C * G / len(passes), avg_launch,
+                                     f"k_board_pass<{t}, {pd}, 5>"),
             "whole_board_same_t": {"value": R2 * C * G * args.steps / wall_big,
                                    "unit": "cell-updates/s"}}
     print(json.dumps(line), flush=True)
@@ -795,7 +952,8 @@ def sweep(args):
                 if h < T:
                     continue
                 cfg = {"t_block": T, "band_rows": h, "prefetch": pd, "layout": layout}
-                wall, dev = time_packed(gol, torch, d_in, d_out, R, C, G, 3, 1, 0, config=cfg)
+                wall, dev = timed_region(torch, lambda: gol.step_packed(d_in, R, C, G, d_out,
+                                                                        config=cfg), 3, 1)
                 print(json.dumps({**cfg, "k": k, "cell_updates_per_s": R * C * G * 3 / dev}),
                       flush=True)
 
@@ -805,13 +963,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2",
-                    choices=["c1", "c2", "c3", "c4", "c5", "copy", "pop", "bounded",
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "c1", "c2", "c3", "c4", "c5", "copy", "pop", "bounded",
                              "strip", "decomp", "valu"])
     ap.add_argument("--requests", type=int, default=4096)
-    ap.add_argument("--rate", type=float, default=2700.0,
-                    help="Poisson arrival rate; requests average 1.08e10 cell-updates, so "
-                         "2700/s offers 2.9e13 cell-updates/s, about half the batched capacity")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="Poisson arrival rate of the served stream; 0 = 0.7 of the batched "
+                         "capacity measured in the same run (default line), or 2700/s "
+                         "(--workload c5)")
+    ap.add_argument("--rates", default="",
+                    help="--workload c5: comma-separated arrival rates to sweep")
     ap.add_argument("--chunk", type=int, default=240)
     ap.add_argument("--plain-requests", type=int, default=4096)
     ap.add_argument("--boards", type=int, default=4096)
@@ -819,11 +980,14 @@ def main():
     ap.add_argument("--compare-t1", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
-                    help="batched workload: skip the one-board-at-a-time comparison (profiling runs)")
+                    help="batched / served workloads: skip the one-at-a-time comparison")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (T = 12, model band)")
     ap.add_argument("--config", default="",
                     help="explicit launch configuration t_block,band_rows,prefetch,layout "
-                         "(layout 1 = one band per wave, 2 = paired bands); skips the autotuner")
+                         "(layout 1 = one band per wave, 2 = paired bands) of a single-board "
+                         "workload; skips the autotuner")
+    ap.add_argument("--config-c3", default="", help="--config for the default line's c3 board")
+    ap.add_argument("--config-c2", default="", help="--config for the default line's c2 board")
     ap.add_argument("--sweep", action="store_true",
                     help="time T in {2,4,8,16} x band heights for the single-board workload")
     args = ap.parse_args()
@@ -838,36 +1002,26 @@ def main():
 
     if args.sweep:
         return sweep(args)
-    if args.workload == "c2":
-        R = C = 16384
-        G, p = 1000, 0.3
-        res, extra = single_board(args, R, C, G, p, "c2")
-        workload = "16384x16384 torus, bit-packed, Bernoulli(0.3), 1000 generations"
+    if args.workload == "all":
+        line = default_line(args)
+    elif args.workload == "c2":
+        line = single_line(args, single_board(args, 16384, 16384, 1000, 0.3, args.config,
+                                              compare_t1=args.compare_t1))
     elif args.workload == "c3":
-        R = C = 65536
-        G, p = 200, 0.5
-        args.compare_t1 = True
-        res, extra = single_board(args, R, C, G, p, "c3")
-        workload = "65536x65536 torus, bit-packed, Bernoulli(0.5), 200 generations"
+        line = single_line(args, single_board(args, 65536, 65536, 200, 0.5, args.config,
+                                              compare_t1=True))
     elif args.workload == "c4":
-        res, extra = batched(args)
-        R = C = None
-        G, p = None, None
-        workload = (f"{args.boards} boards, rows/cols log-uniform [64, 2048], p U(0.1, 0.6), "
-                    "generations U{10..1000}, one batched schedule")
+        line = single_line(args, batched(args))
     elif args.workload == "c1":
-        res, extra, n = host_api(args)
-        args.steps = n
-        R = C = 256
-        G, p = 100, 0.5
-        workload = "256x256 torus, uint8 cells, Bernoulli(0.5), 100 generations, host API"
+        line = single_line(args, host_api(args))
     elif args.workload == "c5":
-        res, extra = served(args)
-        args.steps = 1
-        R = C = None
-        G, p = None, None
-        workload = (f"{args.requests} requests, Poisson {args.rate:g}/s, sides log-uniform "
-                    "[32, 8192], p U(0.05, 0.7), generations U{1..10000}, 64 GiB budget")
+        rates = [float(r) for r in args.rates.split(",") if r] or [args.rate or 2700.0]
+        for rate in rates:
+            line = single_line(args, served(args, rate, plain=not args.no_plain))
+            if len(rates) > 1:
+                print(json.dumps(line), flush=True)
+        if len(rates) > 1:
+            return
     elif args.workload == "copy":
         copy_calibration(args)
         return
@@ -886,35 +1040,6 @@ def main():
     elif args.workload == "valu":
         valu_workload(args)
         return
-    ms = res["wall_s"] / args.steps * 1e3
-    line = {
-        "metric": "cell-updates/sec",
-        "value": res["value"],
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": workload, "rows": R, "cols": C, "generations": G, "p": p,
-                   "seed": SEED, "t_block": getattr(args, "tuned", {}).get("t_block",
-                                                                          args.t_block or 12),
-                   "band_rows": getattr(args, "tuned", {}).get("band_rows"),
-                   "prefetch": getattr(args, "tuned", {}).get("prefetch"),
-                   "layout": {1: "band", 2: "paired"}.get(getattr(args, "tuned", {})
-                                                          .get("layout")),
-                   "parallelism": "single GPU"},
-        "roofline": res["roofline"],
-    }
-    line.update(extra)
-    if not args.no_cpu:
-        log("cpu baseline (oracle)")
-        if args.workload in ("c2", "c3", "c1"):
-            line["cpu_baseline"] = cpu_baseline(min(R, 16384), min(C, 16384), p, SEED)
     print(json.dumps(line), flush=True)
 
 

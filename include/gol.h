@@ -267,7 +267,9 @@ typedef struct {
 } gol_request_info;
 
 int gol_serve_create(const gol_serve_config* cfg, gol_server** out);
-/* Copies rows * W words from host memory before returning. */
+/* Copies rows * W words from host memory before returning (padding bits are
+ * cleared in the copy, so every result -- also of a request of zero
+ * generations -- has them 0). */
 int gol_serve_submit(gol_server* srv, const uint64_t* host_packed, int64_t rows, int64_t cols,
                      int64_t generations, uint64_t* ticket);
 /* GOL_EAGAIN until done; then writes rows * W words to host_out, fills info

@@ -158,6 +158,42 @@ def _ptr(t) -> int:
     return int(t.data_ptr())
 
 
+def _dev_words(t, rows: int, cols: int, name: str, nrows: int | None = None,
+               at_least: bool = False):
+    """A device tensor of packed words: CUDA, C-contiguous, 8-byte elements,
+    exactly (or, with at_least, at least) (nrows or rows) * W of them."""
+    import torch
+    n = (rows if nrows is None else nrows) * words_per_row(cols)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device (cuda) tensor")
+    if t.dtype not in (torch.int64, getattr(torch, "uint64", torch.int64)):
+        raise ValueError(f"{name} must hold 64-bit words (int64), got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n and not (at_least and t.numel() >= n):
+        raise ValueError(f"{name} holds {t.numel()} words, expected {n}")
+    return t
+
+
+def _host_array(a, size: int, dtypes, name: str, writable: bool):
+    """A host numpy array the library reads or writes `size` elements of."""
+    if not isinstance(a, np.ndarray):
+        raise ValueError(f"{name} must be a numpy array")
+    if a.dtype not in dtypes:
+        raise ValueError(f"{name} must have dtype {' or '.join(str(d) for d in dtypes)}, "
+                         f"got {a.dtype}")
+    if not a.flags.c_contiguous:
+        raise ValueError(f"{name} must be C-contiguous")
+    if writable and not a.flags.writeable:
+        raise ValueError(f"{name} must be writable")
+    if a.size != size:
+        raise ValueError(f"{name} holds {a.size} elements, expected {size}")
+    return a
+
+
+_WORD_DTYPES = (np.dtype(np.uint64), np.dtype(np.int64))
+
+
 # ---------------------------------------------------------------------------
 # Single board
 # ---------------------------------------------------------------------------
@@ -169,6 +205,7 @@ def step(board: np.ndarray, generations: int, out: Optional[np.ndarray] = None) 
     if out is None:
         out = np.empty_like(b)
     rows, cols = b.shape
+    _host_array(out, rows * cols, (np.dtype(np.uint8),), "out", writable=True)
     _check(lib().gol_step(b.ctypes.data, rows, cols, int(generations), out.ctypes.data))
     return out
 
@@ -189,8 +226,10 @@ def step_packed(d_in, rows: int, cols: int, generations: int, d_out=None, stream
 
     config: gol_pass_config fields as a dict (t_block, band_rows, prefetch,
     layout; missing or 0 = automatic); when given, t_block is ignored."""
+    _dev_words(d_in, rows, cols, "d_in")
     if d_out is None:
         d_out = empty_packed(rows, cols, d_in.device)
+    _dev_words(d_out, rows, cols, "d_out")
     if config is not None:
         c = PassConfig(**{k: int(v) for k, v in config.items()})
         _check(lib().gol_step_packed_cfg(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
@@ -205,8 +244,10 @@ def step_packed_bounded(d_in, rows: int, cols: int, generations: int, d_out=None
                         config: dict | None = None):
     """step_packed on a bounded board: every cell beyond the edges is dead
     (no torus).  config as for step_packed (band layout only)."""
+    _dev_words(d_in, rows, cols, "d_in")
     if d_out is None:
         d_out = empty_packed(rows, cols, d_in.device)
+    _dev_words(d_out, rows, cols, "d_out")
     c = PassConfig(**{k: int(v) for k, v in (config or {}).items()})
     _check(lib().gol_step_packed_bounded(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
                                          _stream_handle(stream), ctypes.byref(c)))
@@ -218,8 +259,12 @@ def strip_pass(d_strip, d_top, d_bottom, rows: int, cols: int, t: int, d_out=Non
     """t generations of a row strip of a larger torus: d_top holds the t rows
     above the strip (farthest first), d_bottom the t rows below it (nearest
     first); columns wrap.  Returns d_out (the strip at generation + t)."""
+    _dev_words(d_strip, rows, cols, "d_strip")
+    _dev_words(d_top, rows, cols, "d_top", nrows=int(t), at_least=True)
+    _dev_words(d_bottom, rows, cols, "d_bottom", nrows=int(t), at_least=True)
     if d_out is None:
         d_out = empty_packed(rows, cols, d_strip.device)
+    _dev_words(d_out, rows, cols, "d_out")
     c = PassConfig(**{k: int(v) for k, v in (config or {}).items()})
     _check(lib().gol_strip_pass(_ptr(d_strip), _ptr(d_top), _ptr(d_bottom), rows, cols, int(t),
                                 _ptr(d_out), _stream_handle(stream), ctypes.byref(c)))
@@ -240,6 +285,7 @@ def valu_rate(kind: int, stream=None) -> float:
 def population(d_packed, rows: int, cols: int, stream=None) -> int:
     """Live cells of a packed device board (waits for the result)."""
     import torch
+    _dev_words(d_packed, rows, cols, "d_packed")
     cnt = torch.zeros(1, dtype=torch.int64, device=d_packed.device)
     _check(lib().gol_population(_ptr(d_packed), rows, cols, _ptr(cnt), _stream_handle(stream)))
     return int(cnt.item())
@@ -251,8 +297,10 @@ def step_packed_population(d_in, rows: int, cols: int, generations: int, checks,
     in `checks` (non-decreasing, each in 0..generations).  Returns (d_out, counts),
     counts a device int64 tensor with one entry per check (asynchronous)."""
     import torch
+    _dev_words(d_in, rows, cols, "d_in")
     if d_out is None:
         d_out = empty_packed(rows, cols, d_in.device)
+    _dev_words(d_out, rows, cols, "d_out")
     ch = np.ascontiguousarray(list(checks), dtype=np.int64)
     counts = torch.empty(max(1, len(ch)), dtype=torch.int64, device=d_in.device)
     c = PassConfig(**{k: int(v) for k, v in (config or {}).items()})
@@ -278,17 +326,30 @@ def tune_config(rows: int, cols: int, stream=None) -> dict:
     return {f: getattr(c, f) for f, _ in PassConfig._fields_}
 
 
+def _dev_bytes(t, rows: int, cols: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.uint8 or \
+            not t.is_contiguous() or t.numel() != rows * cols:
+        raise ValueError(f"{name} must be a contiguous uint8 device tensor of {rows * cols} "
+                         "cells")
+    return t
+
+
 def pack(d_bytes, rows: int, cols: int, d_out=None, stream=None):
+    _dev_bytes(d_bytes, rows, cols, "d_bytes")
     if d_out is None:
         d_out = empty_packed(rows, cols, d_bytes.device)
+    _dev_words(d_out, rows, cols, "d_out")
     _check(lib().gol_pack(_ptr(d_bytes), rows, cols, _ptr(d_out), _stream_handle(stream)))
     return d_out
 
 
 def unpack(d_packed, rows: int, cols: int, d_out=None, stream=None):
     import torch
+    _dev_words(d_packed, rows, cols, "d_packed")
     if d_out is None:
         d_out = torch.empty((rows, cols), dtype=torch.uint8, device=d_packed.device)
+    _dev_bytes(d_out, rows, cols, "d_out")
     _check(lib().gol_unpack(_ptr(d_packed), rows, cols, _ptr(d_out), _stream_handle(stream)))
     return d_out
 
@@ -308,6 +369,8 @@ class BatchBoard:
 def _board_array(boards: Sequence[BatchBoard]):
     arr = (Board * max(1, len(boards)))()
     for i, b in enumerate(boards):
+        _dev_words(b.d_in, b.rows, b.cols, f"boards[{i}].d_in")
+        _dev_words(b.d_out, b.rows, b.cols, f"boards[{i}].d_out")
         arr[i] = Board(_ptr(b.d_in), _ptr(b.d_out), b.rows, b.cols, b.generations)
     return arr
 
@@ -370,30 +433,48 @@ class Server:
         else:
             _check(lib().gol_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
+        self._shapes: dict[int, tuple[int, int]] = {}  # ticket -> (rows, cols)
 
     def host_peak_bytes(self) -> int:
         return int(lib().gol_debug_serve_host_peak_bytes(self._h))
 
     def submit(self, packed: np.ndarray, rows: int, cols: int, generations: int) -> int:
-        a = np.ascontiguousarray(packed).view(np.uint64)
+        a = np.ascontiguousarray(packed)
+        if a.dtype not in _WORD_DTYPES:
+            raise ValueError(f"packed board must hold 64-bit words, got {a.dtype}")
+        a = a.view(np.uint64)
         if a.size != rows * words_per_row(cols):
             raise ValueError("packed board has the wrong size")
         t = ctypes.c_uint64()
         _check(lib().gol_serve_submit(self._h, a.ctypes.data, rows, cols, int(generations),
                                       ctypes.byref(t)))
+        self._shapes[t.value] = (int(rows), int(cols))
         return t.value
 
+    def _out(self, ticket: int, out: np.ndarray) -> np.ndarray:
+        """The result buffer must hold exactly the ticket's rows * W words."""
+        shape = self._shapes.get(int(ticket))
+        if shape is None:  # never submitted here, or already retired
+            raise GolError(GOL_ENOTFOUND, f"unknown or retired ticket {ticket}")
+        return _host_array(out, shape[0] * words_per_row(shape[1]), _WORD_DTYPES, "out",
+                           writable=True)
+
     def poll(self, ticket: int, out: np.ndarray):
+        self._out(ticket, out)
         info = RequestInfo()
         rc = lib().gol_serve_poll(self._h, ticket, out.ctypes.data, ctypes.byref(info))
         if rc == GOL_EAGAIN:
             return None
+        self._shapes.pop(int(ticket), None)  # retired, failed or cancelled
         _check(rc)
         return info
 
     def wait(self, ticket: int, out: np.ndarray) -> RequestInfo:
+        self._out(ticket, out)
         info = RequestInfo()
-        _check(lib().gol_serve_wait(self._h, ticket, out.ctypes.data, ctypes.byref(info)))
+        rc = lib().gol_serve_wait(self._h, ticket, out.ctypes.data, ctypes.byref(info))
+        self._shapes.pop(int(ticket), None)
+        _check(rc)
         return info
 
     def cancel(self, ticket: int) -> None:

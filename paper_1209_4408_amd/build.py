@@ -30,21 +30,38 @@ def _run(cmd: list[str]) -> None:
         raise RuntimeError("build step failed: " + " ".join(cmd))
 
 
-def build(save_temps: bool = False, out: str = LIB, defines: tuple = ()) -> str:
+def _stale(obj: str, src: str) -> bool:
+    """The object is missing or older than its source or any header."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(d, f) for d in (CSRC, INCLUDE) for f in os.listdir(d)
+                    if f.endswith(".h")]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(save_temps: bool = False, out: str = LIB, defines: tuple = (),
+          incremental: bool = False) -> str:
+    """Compile every source (or, incremental, those whose object is stale) and
+    link libgol.so."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(OBJ, exist_ok=True)
-    objs = []
+    jobs, objs = [], []
     for s in DEVICE_SOURCES:
         o = os.path.join(OBJ, s + ".o")
         cmd = [HIPCC, *COMMON, *DEVICE, *[f"-D{d}" for d in defines], "-c",
                os.path.join(CSRC, s), "-o", o]
         if save_temps:
             cmd += ["-save-temps=obj"]
-        _run(cmd)
-        objs.append(o)
+        jobs.append((cmd, o, os.path.join(CSRC, s)))
     for s in HOST_SOURCES:
         o = os.path.join(OBJ, s + ".o")
-        _run([HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, s), "-o", o])
-        objs.append(o)
+        jobs.append(([HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, s),
+                      "-o", o], o, os.path.join(CSRC, s)))
+    todo = [cmd for cmd, o, src in jobs if not incremental or defines or _stale(o, src)]
+    with ThreadPoolExecutor(max_workers=min(8, max(1, len(todo)))) as ex:
+        list(ex.map(_run, todo))
+    objs = [o for _, o, _ in jobs]
     tmp = out + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"])
     os.replace(tmp, out)
@@ -52,4 +69,4 @@ def build(save_temps: bool = False, out: str = LIB, defines: tuple = ()) -> str:
 
 
 if __name__ == "__main__":
-    print(build(save_temps="--save-temps" in sys.argv))
+    print(build(save_temps="--save-temps" in sys.argv, incremental="--incremental" in sys.argv))

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
 #include <cstdarg>
 #include <cstdio>
 #include <mutex>
@@ -126,19 +127,61 @@ void scratch_free(void* p, hipStream_t st) {
     (void)hipFreeAsync(p, st);
 }
 
-// Pinned host staging that must outlive queued copies: freed once the event
-// recorded after its last use has completed.
-static std::mutex g_defer_mu;
-static std::vector<std::pair<hipEvent_t, void*>> g_deferred;
+// Pinned host staging blocks, reused by power-of-two size class, and a pool
+// of timing-free events, so repeated calls do not call hipHostMalloc or
+// hipEventCreate.  A block handed back with pinned_put_after returns to the
+// pool once the event recorded after its last use has completed.
+static std::mutex g_pin_mu;
+static std::map<size_t, std::vector<void*>> g_pin_free;
+static std::vector<hipEvent_t> g_event_free;
+struct Deferred {
+  hipEvent_t ev;
+  void* pinned;
+  size_t cls;
+};
+static std::vector<Deferred> g_deferred;
+
+void* pinned_get(size_t bytes, size_t* cls_out) {
+  size_t cls = 4096;
+  while (cls < bytes) cls <<= 1;
+  *cls_out = cls;
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto& v = g_pin_free[cls];
+    if (!v.empty()) {
+      void* p = v.back();
+      v.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, cls, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+static hipError_t event_get(hipEvent_t* ev) {
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    if (!g_event_free.empty()) {
+      *ev = g_event_free.back();
+      g_event_free.pop_back();
+      return hipSuccess;
+    }
+  }
+  return hipEventCreateWithFlags(ev, hipEventDisableTiming);
+}
 
 void reap_deferred(bool wait) {
-  std::lock_guard<std::mutex> lk(g_defer_mu);
+  std::lock_guard<std::mutex> lk(g_pin_mu);
   size_t k = 0;
   for (auto& d : g_deferred) {
-    if (wait) (void)hipEventSynchronize(d.first);
-    if (hipEventQuery(d.first) == hipSuccess) {
-      (void)hipEventDestroy(d.first);
-      (void)hipHostFree(d.second);
+    if (wait) (void)hipEventSynchronize(d.ev);
+    if (hipEventQuery(d.ev) == hipSuccess) {
+      g_event_free.push_back(d.ev);
+      g_pin_free[d.cls].push_back(d.pinned);
     } else {
       g_deferred[k++] = d;
     }
@@ -146,13 +189,13 @@ void reap_deferred(bool wait) {
   g_deferred.resize(k);
 }
 
-int defer_host_free(void* pinned, hipStream_t st) {
-  hipEvent_t ev;
-  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+int pinned_put_after(void* pinned, size_t cls, hipStream_t st) {
+  hipEvent_t ev = nullptr;
+  hipError_t e = event_get(&ev);
   if (e == hipSuccess) e = hipEventRecord(ev, st);
   if (e != hipSuccess) return hip_error(e, "hipEventRecord");
-  std::lock_guard<std::mutex> lk(g_defer_mu);
-  g_deferred.emplace_back(ev, pinned);
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_deferred.push_back(Deferred{ev, pinned, cls});
   return GOL_OK;
 }
 
@@ -290,9 +333,41 @@ hipError_t launch_pass(const PassConfig& c, const uint32_t* src, uint32_t* dst, 
                            board_geometry(R, C, c.band_rows), c.pd, c.bounded, st);
 }
 
+// Walks the operations of a run in order without storing them: for each
+// stretch of generations up to the next population check (or to G), the
+// passes -- powers of two for the stretch mod t_block, small first, then whole
+// t_block passes; in the resident layout, launches of at most
+// kResidentMaxGens generations -- then the count at that check.  op(t, slot)
+// is called with t > 0 for a pass of t generations and t == 0 for the count
+// into slot `slot`; it returns false to stop the walk.
+template <class Op>
+static void walk_ops(int64_t G, int T, bool resident, const int64_t* checks, int64_t ncheck,
+                     Op&& op) {
+  int64_t g = 0;
+  for (int64_t i = 0; i <= ncheck; ++i) {
+    const int64_t upto = i < ncheck ? checks[i] : G;
+    const int64_t len = upto - g;
+    if (len > 0 && resident) {
+      for (int64_t left = len; left > 0;) {
+        const int64_t m = std::min<int64_t>(left, kResidentMaxGens);
+        if (!op((int)m, -1)) return;
+        left -= m;
+      }
+    } else if (len > 0) {
+      const int64_t r = len % T;
+      for (int k = 0; (1 << k) < T; ++k)
+        if ((r & (1 << k)) && !op(1 << k, -1)) return;
+      for (int64_t q = len / T; q > 0; --q)
+        if (!op(T, -1)) return;
+    }
+    g = std::max(g, upto);
+    if (i < ncheck && !op(0, i)) return;
+  }
+}
+
 int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t* d_out,
                 hipStream_t st, const PassConfig& cfg, const int64_t* checks, int64_t ncheck,
-                int64_t* d_counts) {
+                int64_t* d_counts, void* ext_scratch, size_t ext_scratch_bytes) {
   int rc = check_board(R, C, G);
   if (rc) return rc;
   if (!d_in || !d_out) return set_error(GOL_EINVAL, "null board pointer");
@@ -310,98 +385,87 @@ int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t*
   const size_t bytes = (size_t)(R * W * 8);
   if (ranges_partially_overlap(d_in, d_out, bytes))
     return set_error(GOL_EINVAL, "d_in and d_out partially overlap");
-  reap_deferred(false);
+  if (ext_scratch && bytes > ext_scratch_bytes)
+    return set_error(GOL_EINVAL,
+                     "the board needs %zu bytes of scratch; the fixed scratch holds %zu",
+                     bytes, ext_scratch_bytes);
+  if (!ext_scratch) reap_deferred(false);
+  const bool resident = c.layout == kLayoutResident;
   unsigned long long* counts = (unsigned long long*)d_counts;
   hipError_t e = hipSuccess;
   if (ncheck > 0) e = launch_fill_u32((uint32_t*)d_counts, 2 * ncheck, 0u, st);
-  // Operations in order: a pass of T > 0 generations, or (T == 0) a count of
-  // the current board into slot `slot`.  A pass ends at every checked
-  // generation, and the board it leaves is counted (one read of the board).
-  struct Op {
-    int T;
-    int64_t slot;
-  };
-  std::vector<Op> ops;
-  int64_t g = 0;
-  for (int64_t i = 0; i <= ncheck; ++i) {
-    const int64_t upto = i < ncheck ? checks[i] : G;
-    if (upto > g && c.layout == kLayoutResident) {
-      // one launch runs the generations up to the next check, at most
-      // kResidentMaxGens of them, so that no single launch holds the device
-      // for long
-      for (int64_t left = upto - g; left > 0; left -= std::min<int64_t>(left, kResidentMaxGens))
-        ops.push_back(Op{(int)std::min<int64_t>(left, kResidentMaxGens), -1});
-      g = upto;
-    } else if (upto > g) {
-      for (int t : single_board_passes(upto - g, c.T)) ops.push_back(Op{t, -1});
-      g = upto;
-    }
-    if (i < ncheck) ops.push_back(Op{0, i});
-  }
-  int K = 0;
-  for (const Op& o : ops) K += o.T > 0;
+  // passes in the run (a pass ends at every checked generation)
+  int64_t K = 0;
+  walk_ops(G, c.T, resident, checks, ncheck, [&](int t, int64_t) {
+    K += t > 0;
+    return true;
+  });
   if (K == 0) {
     if (e == hipSuccess) e = launch_copy_clear_padding(d_in, R, C, d_out, st);
-    for (const Op& o : ops)
-      if (e == hipSuccess) e = launch_population(d_out, R, C, counts + o.slot, st);
+    for (int64_t i = 0; i < ncheck && e == hipSuccess; ++i)
+      e = launch_population(d_out, R, C, counts + i, st);
     return e == hipSuccess ? GOL_OK : hip_error(e, "copy kernel launch");
   }
-  if (c.layout == kLayoutResident) {
+  if (resident) {
     // each launch reads its whole board before writing, so every launch
     // after the first runs in place on d_out
     const int32_t D = (int32_t)(2 * W);
     const uint32_t* cur = (const uint32_t*)d_in;
-    for (const Op& o : ops) {
-      if (e != hipSuccess) break;
-      if (o.T == 0) {
-        e = launch_population((const uint64_t*)cur, R, C, counts + o.slot, st);
-        continue;
-      }
-      e = launch_board_lds(cur, (uint32_t*)d_out, (int32_t)R, (int32_t)C, D, o.T, st);
-      cur = (const uint32_t*)d_out;
-    }
+    walk_ops(G, c.T, true, checks, ncheck, [&](int t, int64_t slot) {
+      if (t == 0)
+        e = launch_population((const uint64_t*)cur, R, C, counts + slot, st);
+      else
+        e = launch_board_lds(cur, (uint32_t*)d_out, (int32_t)R, (int32_t)C, D, t, st);
+      if (t > 0) cur = (const uint32_t*)d_out;
+      return e == hipSuccess;
+    });
     return e == hipSuccess ? GOL_OK : hip_error(e, "resident board launch");
   }
-  void* s1v = nullptr;
-  rc = scratch_alloc(&s1v, bytes, st);
-  if (rc) return rc;
+  void* s1v = ext_scratch;
+  if (!s1v) {
+    rc = scratch_alloc(&s1v, bytes, st);
+    if (rc) return rc;
+  }
   uint32_t* s1 = (uint32_t*)s1v;
   uint32_t* out = (uint32_t*)d_out;
   const uint32_t* src0 = (const uint32_t*)d_in;
   uint32_t* w[2] = {out, s1};
-  int par = (K - 1) & 1;
+  int par = (int)((K - 1) & 1);
   if (e == hipSuccess && (const void*)d_in == (const void*)d_out && (K & 1)) {
     // pass 0 must not write the board it reads: start from a copy
     e = launch_copy_clear_padding(d_in, R, C, (uint64_t*)s1, st);
     src0 = s1;
     par = 0;
   }
+  // the G mod T remainder: shorter passes, one band per wave, defaults
+  PassConfig rem;
+  rem.layout = kLayoutBand;
+  rem.bounded = c.bounded;
   const uint32_t* cur = src0;  // the board after the passes so far
-  int j = 0;
-  for (const Op& o : ops) {
-    if (e != hipSuccess) break;
-    if (o.T == 0) {
-      e = launch_population((const uint64_t*)cur, R, C, counts + o.slot, st);
-      continue;
-    }
-    const uint32_t* src = (j == 0) ? src0 : w[(j - 1 + par) & 1];
-    uint32_t* dst = w[(j + par) & 1];
-    if (o.T == c.T) {
-      e = launch_pass(c, src, dst, R, C, st);
-    } else {
-      // the G mod T remainder: shorter passes, one band per wave, defaults
-      PassConfig r;
-      r.T = o.T;
-      r.layout = kLayoutBand;
-      r.bounded = c.bounded;
-      r.pd = default_prefetch(r.T);
-      r.band_rows = default_band_rows(R, C, r.T, simd_count());
-      e = launch_pass(r, src, dst, R, C, st);
-    }
-    cur = dst;
-    ++j;
-  }
-  scratch_free(s1v, st);
+  int64_t j = 0;
+  if (e == hipSuccess)
+    walk_ops(G, c.T, false, checks, ncheck, [&](int t, int64_t slot) {
+      if (t == 0) {
+        e = launch_population((const uint64_t*)cur, R, C, counts + slot, st);
+        return e == hipSuccess;
+      }
+      const uint32_t* src = (j == 0) ? src0 : w[(j - 1 + par) & 1];
+      uint32_t* dst = w[(j + par) & 1];
+      if (t == c.T) {
+        e = launch_pass(c, src, dst, R, C, st);
+      } else {
+        if (rem.T != t) {
+          rem.T = t;
+          rem.pd = default_prefetch(t);
+          rem.band_rows = default_band_rows(R, C, t, simd_count());
+        }
+        e = launch_pass(rem, src, dst, R, C, st);
+      }
+      cur = dst;
+      ++j;
+      return e == hipSuccess;
+    });
+  if (!ext_scratch) scratch_free(s1v, st);
   if (e != hipSuccess) return hip_error(e, "tile pass launch");
   return GOL_OK;
 }
@@ -691,22 +755,22 @@ int batch_run(const gol_board* boards, int64_t n, hipStream_t st, int T) {
     scratch_free(scratch, st);
     return rc;
   }
-  void* pinned = nullptr;
-  hipError_t e = hipHostMalloc(&pinned, mb, hipHostMallocDefault);
-  if (e != hipSuccess) {
+  size_t cls = 0;
+  void* pinned = pinned_get(mb, &cls);
+  if (!pinned) {
     scratch_free(meta, st);
     scratch_free(scratch, st);
-    return set_error(GOL_ENOMEM, "hipHostMalloc(%zu): %s", mb, hipGetErrorString(e));
+    return set_error(GOL_ENOMEM, "pinned staging of %zu bytes", mb);
   }
   fill_meta_host(P, (char*)pinned, ob, os, oi);
-  e = hipMemcpyAsync(meta, pinned, mb, hipMemcpyHostToDevice, st);
+  hipError_t e = hipMemcpyAsync(meta, pinned, mb, hipMemcpyHostToDevice, st);
   P.d_boards = (BoardDesc*)((char*)meta + ob);
   P.d_segs = (Segment*)((char*)meta + os);
   P.d_items = (WaveItem*)((char*)meta + oi);
   if (e == hipSuccess) e = enqueue_plan(P, st, side.st, side.fork, side.join);
   scratch_free(meta, st);
   scratch_free(scratch, st);
-  rc = defer_host_free(pinned, st);
+  rc = pinned_put_after(pinned, cls, st);
   if (e != hipSuccess) return hip_error(e, "gol_batch_run");
   return rc;
 }
@@ -726,7 +790,28 @@ struct gol_plan {
   hipGraphExec_t exec = nullptr;
   hipStream_t side = nullptr;  // the late group's stream (default priority)
   hipEvent_t fork = nullptr, join = nullptr;
+  // one event recorded after each run still in flight: destroy waits for
+  // these only, not for the whole device
+  std::vector<hipEvent_t> runs;
+  std::mutex mu;
 };
+
+// Records the end of a plan run on `st` (reusing events of completed runs).
+static hipError_t plan_mark_run(gol_plan* p, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipEvent_t ev = nullptr;
+  for (size_t i = 0; i < p->runs.size(); ++i)
+    if (hipEventQuery(p->runs[i]) == hipSuccess) {
+      ev = p->runs[i];
+      p->runs.erase(p->runs.begin() + (long)i);
+      break;
+    }
+  hipError_t e = ev ? hipSuccess : hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev, st);
+  if (e == hipSuccess) p->runs.push_back(ev);
+  else if (ev) (void)hipEventDestroy(ev);
+  return e;
+}
 
 extern "C" {
 
@@ -970,6 +1055,7 @@ int gol_plan_run(gol_plan* p, void* stream) {
   hipStream_t st = (hipStream_t)stream;
   if (st == nullptr) {
     hipError_t e = enqueue_plan(p->P, st, p->side, p->fork, p->join);
+    if (e == hipSuccess) e = plan_mark_run(p, st);
     return e == hipSuccess ? GOL_OK : hip_error(e, "gol_plan_run");
   }
   if (!p->exec) {
@@ -992,6 +1078,7 @@ int gol_plan_run(gol_plan* p, void* stream) {
     p->graph = g;
   }
   hipError_t e = hipGraphLaunch(p->exec, st);
+  if (e == hipSuccess) e = plan_mark_run(p, st);
   return e == hipSuccess ? GOL_OK : hip_error(e, "hipGraphLaunch");
 }
 
@@ -1005,7 +1092,13 @@ int gol_plan_info(const gol_plan* p, int64_t* waves, int64_t* levels, double* ce
 
 int gol_plan_destroy(gol_plan* p) {
   if (!p) return GOL_OK;
-  (void)hipDeviceSynchronize();
+  // the plan's buffers and graph are in use until its queued runs end
+  for (hipEvent_t ev : p->runs) {
+    (void)hipEventSynchronize(ev);
+    (void)hipEventDestroy(ev);
+  }
+  p->runs.clear();
+  if (p->side) (void)hipStreamSynchronize(p->side);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->meta) (void)hipFree(p->meta);

@@ -61,15 +61,6 @@ bool paired_ok(int64_t rows, int64_t cols, int T, const GridGeom& g, const char*
   return w == nullptr;
 }
 
-std::vector<int> single_board_passes(int64_t generations, int T) {
-  std::vector<int> p;
-  const int64_t r = generations % T;
-  for (int k = 0; (1 << k) < T; ++k)
-    if (r & (1 << k)) p.push_back(1 << k);
-  for (int64_t i = 0; i < generations / T; ++i) p.push_back(T);
-  return p;
-}
-
 // Throughput of the tile pass relative to its best, against resident waves
 // per SIMD (measured on MI355X for 16384^2 and 65536^2 boards after removing
 // the halo-row overhead; the two boards agree): latency is hidden better

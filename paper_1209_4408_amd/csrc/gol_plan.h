@@ -73,10 +73,6 @@ GridGeom paired_geometry(int64_t rows, int64_t cols, int band_rows, int T, int p
 // grid g; if not, *why says which condition fails.
 bool paired_ok(int64_t rows, int64_t cols, int T, const GridGeom& g, const char** why);
 
-// Pass lengths of a single board: powers of two for G mod T (small first),
-// then whole T passes.  Sum = G.  Every length is a valid_board_T.
-std::vector<int> single_board_passes(int64_t generations, int T);
-
 // Builds the batch schedule.  Returns false with a message on invalid input.
 bool build_plan(const std::vector<BoardReq>& boards, int T, int band_rows, HostPlan& plan,
                 std::string& err);

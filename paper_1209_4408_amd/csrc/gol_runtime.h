@@ -20,7 +20,11 @@ const char* last_error();
 
 int scratch_alloc(void** p, size_t bytes, hipStream_t st);
 void scratch_free(void* p, hipStream_t st);
-int defer_host_free(void* pinned, hipStream_t st);
+// Pinned host staging from a pool of power-of-two size classes (*cls
+// receives the class); pinned_put_after returns the block to the pool once
+// the work queued on st so far has run.
+void* pinned_get(size_t bytes, size_t* cls);
+int pinned_put_after(void* pinned, size_t cls, hipStream_t st);
 void reap_deferred(bool wait);
 
 int check_board(int64_t rows, int64_t cols, int64_t gens);
@@ -48,10 +52,14 @@ hipError_t launch_pass(const PassConfig& c, const uint32_t* src, uint32_t* dst, 
                        int64_t C, hipStream_t st);
 
 // checks (host, non-decreasing, in 0..G) / d_counts (device int64[ncheck]):
-// the population after each checked generation count.
+// the population after each checked generation count.  ext_scratch (device,
+// ext_scratch_bytes): the ping-pong board to use instead of one from the
+// allocator (boards larger than it -> GOL_EINVAL); with it the call makes no
+// device or pinned allocation.
 int step_packed(const uint64_t* d_in, int64_t R, int64_t C, int64_t G, uint64_t* d_out,
                 hipStream_t st, const PassConfig& cfg, const int64_t* checks = nullptr,
-                int64_t ncheck = 0, int64_t* d_counts = nullptr);
+                int64_t ncheck = 0, int64_t* d_counts = nullptr, void* ext_scratch = nullptr,
+                size_t ext_scratch_bytes = 0);
 
 // A batch schedule bound to device buffers.
 struct DevicePlan {

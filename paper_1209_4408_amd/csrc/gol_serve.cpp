@@ -772,6 +772,13 @@ int gol_serve_submit(gol_server* srv, const uint64_t* host_packed, int64_t rows,
     r->pin_in = S.exec->host_alloc(bytes, &r->pin_in_cls);
     if (!r->pin_in) return set_error(GOL_ENOMEM, "pinned staging for %zu bytes", bytes);
     memcpy(r->pin_in, host_packed, bytes);
+    if (cols % 64) {
+      // padding bits are not cells: the server keeps every board with them
+      // cleared, so a request of zero generations returns the normalised input
+      const uint64_t keep = ((uint64_t)1 << (cols % 64)) - 1;
+      uint64_t* last = (uint64_t*)r->pin_in + (W - 1);
+      for (int64_t i = 0; i < rows; ++i) last[i * W] &= keep;
+    }
     std::lock_guard<std::mutex> lk(S.mu);
     if (S.failed) {
       S.exec->host_free(r->pin_in, r->pin_in_cls);

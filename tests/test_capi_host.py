@@ -255,3 +255,51 @@ def test_valu_probe_rejects_bad_kinds_before_any_device_work():
     assert L.gol_debug_valu_rate(-1, None, C.byref(r)) == -1
     assert L.gol_debug_valu_rate(5, None, C.byref(r)) == -1
     assert L.gol_debug_valu_rate(0, None, None) == -1
+
+
+def test_binding_rejects_bad_host_buffers():
+    """The binding checks every host buffer the library writes before the call:
+    a short, wrongly typed, non-contiguous or read-only array is a ValueError,
+    never an out-of-bounds write."""
+    b = np.zeros((5, 70), np.uint8)
+    for bad in (np.zeros((5, 69), np.uint8), np.zeros((5, 70), np.int32),
+                np.zeros((5, 140), np.uint8)[:, ::2]):
+        with pytest.raises(ValueError):
+            gol.step(b, 1, out=bad)
+    ro = np.zeros((5, 70), np.uint8)
+    ro.flags.writeable = False
+    with pytest.raises(ValueError):
+        gol.step(b, 1, out=ro)
+    with gol.Server(hbm_budget_bytes=1 << 20, chunk_generations=4, host_executor=True) as srv:
+        w = np.zeros((6, 2), np.uint64)
+        t = srv.submit(w, 6, 100, 3)
+        for bad in (np.zeros((6, 1), np.uint64), np.zeros((6, 2), np.uint32),
+                    np.zeros((6, 4), np.uint64)[:, ::2], np.zeros(11, np.uint64)):
+            with pytest.raises(ValueError):
+                srv.wait(t, bad)
+            with pytest.raises(ValueError):
+                srv.poll(t, bad)
+        out = np.zeros((6, 2), np.uint64)
+        srv.wait(t, out)  # the ticket is still good after the rejected calls
+        with pytest.raises(gol.GolError) as e:
+            srv.poll(t, out)
+        assert e.value.code == gol.GOL_ENOTFOUND
+        with pytest.raises(ValueError):
+            srv.submit(np.zeros((6, 2), np.float64), 6, 100, 1)
+        with pytest.raises(ValueError):
+            srv.submit(np.zeros((6, 1), np.uint64), 6, 100, 1)
+
+
+def test_binding_rejects_host_or_wrongly_sized_tensors():
+    """Device entry points take device tensors of exactly rows * W int64 words;
+    anything else is refused before the library sees a pointer."""
+    import torch
+    cpu = torch.zeros((4, 2), dtype=torch.int64)
+    with pytest.raises(ValueError):
+        gol.step_packed(cpu, 4, 100, 1)
+    with pytest.raises(ValueError):
+        gol.population(cpu, 4, 100)
+    with pytest.raises(ValueError):
+        gol.strip_pass(cpu, cpu, cpu, 4, 100, 1)
+    with pytest.raises(ValueError):
+        gol.batch_run([gol.BatchBoard(cpu, cpu, 4, 100, 1)])

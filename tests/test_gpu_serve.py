@@ -124,6 +124,22 @@ def test_serve_zero_generations_and_poll_loop():
         assert e.value.code == gol.GOL_ENOTFOUND
 
 
+@pytest.mark.parametrize("G", [0, 1, 9])
+def test_serve_dirty_padding_is_ignored_and_cleared(G):
+    """Padding bits set on input: a served result equals the oracle on the
+    board's cells and has its padding bits cleared, also with zero generations."""
+    R, C = 21, 70
+    b = rand_bytes(5, 5, R, C, 0.45)
+    w = oracle.pack(b)
+    dirty = w.copy()
+    dirty[:, -1] |= np.uint64(~((1 << (C % 64)) - 1) & (2**64 - 1))
+    with gol.Server(hbm_budget_bytes=1 << 26, chunk_generations=4) as srv:
+        out = np.full_like(w, 0xFFFF)
+        srv.wait(srv.submit(dirty, R, C, G), out)
+    assert oracle.padding_is_zero(out, C)
+    assert np.array_equal(out, oracle.pack(oracle.life(b, G)))
+
+
 def test_serve_stream_poisson_small():
     """A short open-loop stream with requests arriving while others run."""
     specs = seeded_inputs.serve_specs(1209, n=60, rate_per_s=2000.0, side_hi=700, gen_hi=200)

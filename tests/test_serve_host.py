@@ -19,11 +19,25 @@ import paper_1209_4408_amd as gol
 GOL_ENOMEM, GOL_EINVAL, GOL_EDEVICE, GOL_ENOTFOUND, GOL_ECANCELED = -2, -1, -3, -5, -6
 
 
-def board(seed, rows, cols):
+def padding_mask(cols):
+    """Bits of a row's last word that are cells (the rest is padding)."""
+    r = cols % 64
+    return np.uint64(2**64 - 1) if r == 0 else np.uint64((1 << r) - 1)
+
+
+def normalised(w, cols):
+    """The board with its padding bits cleared, as the server keeps it."""
+    n = w.copy()
+    n[:, -1] &= padding_mask(cols)
+    return n
+
+
+def board(seed, rows, cols, dirty=False):
+    """Random words; padding bits clear unless dirty (the server clears them)."""
     rng = np.random.default_rng(seed)
     w = rng.integers(0, 2**64, size=(rows, gol.words_per_row(cols)), dtype=np.uint64)
     w.flat[0] = np.uint64(2**64 - 3)  # the stand-in's addition must wrap
-    return w
+    return w if dirty else normalised(w, cols)
 
 
 def expect(w, g):
@@ -165,6 +179,23 @@ def test_zero_generation_request_returns_its_input():
         srv.wait(srv.submit(w, 9, 130, 0), out)
         assert srv.stats()["chunks"] == 0
     assert np.array_equal(out, w)
+
+
+@pytest.mark.parametrize("cols", [1, 63, 64, 65, 130, 200])
+@pytest.mark.parametrize("G", [0, 5])
+def test_input_padding_bits_are_cleared(cols, G):
+    """Padding bits (columns >= cols) are ignored on input: the server keeps the
+    board with them cleared, so a zero-generation request returns the
+    normalised input and chunks start from it (the stand-in then adds G)."""
+    R = 7
+    w = board(11, R, cols, dirty=True)
+    with gol.Server(hbm_budget_bytes=1 << 20, chunk_generations=3,
+                    host_executor=True) as srv:
+        out = np.zeros_like(w)
+        srv.wait(srv.submit(w, R, cols, G), out)
+    assert np.array_equal(out, expect(normalised(w, cols), G))
+    if G == 0:
+        assert np.array_equal(out, normalised(w, cols))
 
 
 def test_cancel_resident_and_queued():
