@@ -83,6 +83,24 @@ int gol_step_packed_ex(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t
                        uint64_t* d_out, void* stream, int t_block);
 
 /*
+ * gol_step_packed for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, result and automatic configuration as gol_step_packed, but
+ * the ping-pong board comes from a fixed array in the library's device code
+ * (64 MiB on each GPU the library runs on, held until the process ends)
+ * instead of the memory pool or the installed allocator: the call makes no
+ * device or host-pinned allocation and frees nothing.
+ *   Size limit: rows * ceil(cols / 64) * 8 <= 64 MiB (e.g. 16384 x 32768);
+ *   larger boards -> GOL_EINVAL with a message, before any device work.
+ *   Sharing: every call on one GPU uses that GPU's one array, whose contents
+ *   are left from the last call (nothing in it needs clearing: every pass
+ *   writes each word it later reads).  Calls that overlap on one GPU (two
+ *   streams, two threads) race on it; the caller serialises them.
+ */
+int gol_step_packed_noalloc(const uint64_t* d_in, int64_t rows, int64_t cols,
+                            int64_t generations, uint64_t* d_out, void* stream);
+
+/*
  * Launch configuration of the single-board tile pass (Section 2's grid,
  * split into tiles that each advance t_block generations per sweep of the
  * board).  A field of 0 means automatic: when t_block and layout are both 0

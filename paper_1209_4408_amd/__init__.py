@@ -86,6 +86,7 @@ def lib():
             "gol_step": (c_int, [vp, i64, i64, i64, vp]),
             "gol_step_packed": (c_int, [vp, i64, i64, i64, vp, vp]),
             "gol_step_packed_ex": (c_int, [vp, i64, i64, i64, vp, vp, c_int]),
+            "gol_step_packed_noalloc": (c_int, [vp, i64, i64, i64, vp, vp]),
             "gol_tune": (c_int, [i64, i64, vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
             "gol_step_packed_cfg": (c_int, [vp, i64, i64, i64, vp, vp,
                                             ctypes.POINTER(PassConfig)]),
@@ -237,6 +238,21 @@ def step_packed(d_in, rows: int, cols: int, generations: int, d_out=None, stream
     else:
         _check(lib().gol_step_packed_ex(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
                                         _stream_handle(stream), int(t_block)))
+    return d_out
+
+
+# Largest packed board (bytes) gol_step_packed_noalloc takes: its fixed scratch.
+NOALLOC_MAX_BYTES = 64 << 20
+
+
+def step_packed_noalloc(d_in, rows: int, cols: int, generations: int, d_out, stream=None):
+    """step_packed through gol_step_packed_noalloc: the library allocates
+    nothing (its ping-pong board is a fixed device array), so d_out must be
+    given; boards above NOALLOC_MAX_BYTES raise GolError (GOL_EINVAL)."""
+    _dev_words(d_in, rows, cols, "d_in")
+    _dev_words(d_out, rows, cols, "d_out")
+    _check(lib().gol_step_packed_noalloc(_ptr(d_in), rows, cols, int(generations), _ptr(d_out),
+                                         _stream_handle(stream)))
     return d_out
 
 

@@ -41,6 +41,8 @@ hipError_t launch_pack(const uint8_t* in, int64_t R, int64_t C, uint64_t* out, h
 hipError_t launch_unpack(const uint64_t* in, int64_t R, int64_t C, uint8_t* out, hipStream_t st);
 hipError_t launch_copy_clear_padding(const uint64_t* in, int64_t R, int64_t C, uint64_t* out,
                                      hipStream_t st);
+// Device address of the current device's fixed scratch (kFixedScratchBytes).
+hipError_t fixed_scratch(void** out);
 
 // ---------------------------------------------------------------------------
 // Errors
@@ -835,6 +837,31 @@ int gol_step_packed_ex(const uint64_t* d_in, int64_t rows, int64_t cols, int64_t
     PassConfig cfg;
     cfg.T = t_block;
     return step_packed(d_in, rows, cols, generations, d_out, (hipStream_t)stream, cfg);
+  } catch (const std::bad_alloc&) {
+    return set_error(GOL_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return set_error(GOL_EDEVICE, "unexpected exception");
+  }
+}
+
+int gol_step_packed_noalloc(const uint64_t* d_in, int64_t rows, int64_t cols,
+                            int64_t generations, uint64_t* d_out, void* stream) {
+  try {
+    int rc = check_board(rows, cols, generations);
+    if (rc) return rc;
+    const int64_t W = (cols + 63) / 64;
+    if (rows > kFixedScratchBytes / 8 / W)
+      return set_error(GOL_EINVAL,
+                       "gol_step_packed_noalloc takes boards of at most %lld bytes "
+                       "(rows * ceil(cols / 64) * 8); this one needs %lld",
+                       (long long)kFixedScratchBytes, (long long)(rows * W * 8));
+    if (!d_in || !d_out) return set_error(GOL_EINVAL, "null board pointer");
+    void* scr = nullptr;
+    const hipError_t e = fixed_scratch(&scr);
+    if (e != hipSuccess) return hip_error(e, "fixed scratch lookup");
+    PassConfig cfg;
+    return step_packed(d_in, rows, cols, generations, d_out, (hipStream_t)stream, cfg, nullptr,
+                       0, nullptr, scr, (size_t)kFixedScratchBytes);
   } catch (const std::bad_alloc&) {
     return set_error(GOL_ENOMEM, "host allocation failed");
   } catch (...) {

@@ -21,6 +21,11 @@ constexpr int kStripDwords = kWave - 2;
 // Useful columns of a strip in one half of a wave (paired layout).
 constexpr int kHalfStripDwords = kWave / 2 - 2;
 
+// Fixed device scratch of gol_step_packed_noalloc: one ping-pong board of at
+// most this many bytes, a device array of the code object (each GPU the
+// library runs on holds its own copy until the process ends).
+constexpr int64_t kFixedScratchBytes = (int64_t)64 << 20;
+
 // Layouts of the single-board tile pass.
 constexpr int kLayoutBand = 1;    // one band of one strip per wave
 constexpr int kLayoutPaired = 2;  // two adjacent bands per wave, sharing their edge

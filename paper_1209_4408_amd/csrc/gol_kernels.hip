@@ -37,6 +37,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <vector>
+
 #include "gol_internal.h"
 
 // Which instruction kinds the scheduler may move across a row step's load
@@ -1130,6 +1133,38 @@ hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Fixed scratch for callers that cannot allocate (gol_step_packed_noalloc):
+// the ping-pong board of a run lives in this array instead of memory from
+// the allocator.  In host code `scratch` names a host-side stand-in, not the
+// device array, so host code never passes it to a kernel or a copy: it takes
+// the device address from fixed_scratch(), looked up once per device with
+// hipGetSymbolAddress (each GPU holds its own copy at its own address).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint64_t scratch[kFixedScratchBytes / sizeof(uint64_t)];
+
+// Device address of the current device's `scratch` (GOL_OK-style 0, or the
+// HIP error of the lookup).
+hipError_t fixed_scratch(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> ptr;  // per device ordinal, null until looked up
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)ptr.size() <= dev) ptr.resize((size_t)dev + 1, nullptr);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace gol
