@@ -10,9 +10,12 @@ CPU oracle baseline:
   c2  16384 x 16384, Bernoulli(0.3), 1000 generations (plain single board);
   c4  4096 boards of uneven sizes and generation counts in one batched
       schedule, against the plain path (one gol_step_packed per board);
-  c5  an open-loop Poisson request stream through the continuous-batching
-      server (throughput, p50 / p99 latency), against a one-request-at-a-time
-      server on the same trace;
+  c5  4096 requests of uneven sizes and generation counts through the
+      continuous-batching server: the same boards as one batched schedule
+      (the capacity), all requests at once (saturated), and open-loop Poisson
+      streams at 0.3, 0.5, 0.7 and 0.9 of that capacity (throughput, p50 /
+      p99 latency; 0.7 is the block's value), against a one-request-at-a-time
+      server on the 0.7 trace;
   c1  a 256 x 256 byte board, 100 generations, through the host API.
 A "step" of a block is one pass of its whole workload: one board run (c3, c2),
 one schedule over all 4096 boards (c4), one stream of requests (c5).
@@ -53,11 +56,10 @@ ISSUED_OPS_PER_CELL_UPDATE = 12.0 / 32.0
 # Algorithmic HBM bytes per cell-update of a one-generation pass: read + write
 # one bit.
 BYTES_PER_CELL_UPDATE_T1 = 2.0 / 8.0
-# Generations per pass of the batched and served schedules (the library's
-# default, passed explicitly so the reported configuration is the one run).
-BATCH_T = 16
 
 SEED = 1209
+# client threads submitting the saturated stream
+SAT_SUBMITTERS = 4
 
 
 def log(*a):
@@ -94,10 +96,11 @@ def _median_rate(fn, work, reps=3):
 # ---------------------------------------------------------------------------
 # CPU oracle baselines (bounded samples of each workload)
 # ---------------------------------------------------------------------------
-def cpu_baseline_board(rows, cols, p, seed, total_gens, budget_s=15.0):
+def cpu_baseline_board(rows, cols, p, seed, total_gens, budget_s=15.0, gens=0):
     """The oracle (plain C, row decomposition over OpenMP threads) on a bounded
     number of generations of the workload's own board: median of three timed
-    samples; the oracle's single-thread rate beside it."""
+    samples sized to the budget, or one timing of exactly `gens` generations;
+    the oracle's single-thread rate beside it."""
     import oracle
     import seeded_inputs
     threads = cpu_threads()
@@ -105,13 +108,18 @@ def cpu_baseline_board(rows, cols, p, seed, total_gens, budget_s=15.0):
     t0 = time.perf_counter()
     cur = oracle.life(b, 1, threads=threads)
     one = time.perf_counter() - t0
-    g = int(max(1, min(total_gens, budget_s / 3.0 / max(one, 1e-6))))
-    value, rates = _median_rate(lambda: oracle.life(cur, g, threads=threads), rows * cols * g)
+    if gens:
+        g, reps = gens, 1
+    else:
+        g, reps = int(max(1, min(total_gens, budget_s / 3.0 / max(one, 1e-6)))), 3
+    value, rates = _median_rate(lambda: oracle.life(cur, g, threads=threads), rows * cols * g,
+                                reps=reps)
     g1 = int(max(1, min(total_gens, 2.0 / max(one * threads, 1e-6))))
     single, _ = _median_rate(lambda: oracle.life(cur, g1, threads=1), rows * cols * g1, reps=1)
+    timing = "median of 3 timings" if reps == 3 else "one timing"
     return {"value": value, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{g} of the run's {total_gens} generations of the {rows}x{cols} board, "
-                      f"median of 3 timings, {threads} OpenMP threads (row decomposition), "
+                      f"{timing}, {threads} OpenMP threads (row decomposition), "
                       f"byte-per-cell C oracle",
             "rates": rates, "single_thread_value": single,
             "single_thread_sample": f"{g1} generations, 1 thread", "cpu_model": cpu_model()}
@@ -267,7 +275,7 @@ def resolve_config(gol, R, C, args, fixed):
     return cfg
 
 
-def single_board(args, R, C, G, p, fixed_cfg="", compare_t1=False, cpu=True):
+def single_board(args, R, C, G, p, fixed_cfg="", compare_t1=False, cpu=True, cpu_gens=0):
     """One board of R x C cells, G generations, in the autotuned configuration.
 
     Timed regions: (1) the whole run, `steps` times -> value; (2) the
@@ -329,7 +337,7 @@ def single_board(args, R, C, G, p, fixed_cfg="", compare_t1=False, cpu=True):
     torch.cuda.empty_cache()
     if cpu and not args.no_cpu:
         log(f"cpu baseline (oracle) on {R}x{C}")
-        blk["cpu_baseline"] = cpu_baseline_board(R, C, p, SEED, G)
+        blk["cpu_baseline"] = cpu_baseline_board(R, C, p, SEED, G, gens=cpu_gens)
     return blk
 
 
@@ -361,12 +369,14 @@ def batched(args, cpu=True):
     work = float(sum(s.rows * s.cols * s.generations for s in specs))
     log(f"generating {len(specs)} boards, {work:.3e} cell-updates")
     _, d_in, d_out, ins, outs = board_set_device(specs, SEED)
-    T = args.t_block or BATCH_T
     boards = [gol.BatchBoard(i, o, s.rows, s.cols, s.generations)
               for s, i, o in zip(specs, ins, outs)]
     st = torch.cuda.Stream()
-    plan = gol.Plan(boards, t_block=T)
+    log("creating the plan (tuned unless --t-block)")
+    plan = gol.Plan(boards, t_block=args.t_block)
     info = plan.info()
+    pcfg = plan.config()
+    T = pcfg["t_block"]
     log(f"timing the batched schedule: {args.steps} steps after {args.warmup} warmup")
     with torch.cuda.stream(st):
         wall, dev = timed_region(torch, lambda: plan.run(st), args.steps, args.warmup, st)
@@ -383,7 +393,8 @@ def batched(args, cpu=True):
            "config": {"workload": f"{len(specs)} boards, rows/cols log-uniform [64, 2048], "
                                   "p U(0.1, 0.6), generations U{10..1000}, one batched "
                                   "schedule", "boards": len(specs), "seed": SEED,
-                      "t_block": T, "cell_updates": work},
+                      "t_block": T, "band_rows": pcfg["band_rows"],
+                      "tuned": not args.t_block, "cell_updates": work},
            "roofline": roof, "plan": info}
     if not args.no_plain:
         log("plain per-board loop (library default configuration)")
@@ -467,22 +478,16 @@ def nearest_rank(xs, q):
     return xs[k - 1]
 
 
-def served(args, rate, cpu=True, plain=True):
-    """Open-loop Poisson stream through the continuous-batching server, against
-    a one-request-at-a-time server (gol_step_packed per request) on the same
-    trace.  Latency = completion - scheduled arrival."""
+def serve_stream(gol, specs, payloads, rate, args, saturate=False):
+    """One open-loop stream through a fresh continuous-batching server:
+    request i is submitted at its scheduled Poisson arrival (all at once when
+    saturate), a second thread waits for the results in order.  Returns the
+    results, the server's completion times, its clock at the first arrival
+    and its counters."""
     import threading
-    import torch
-    import paper_1209_4408_amd as gol
-    import seeded_inputs
-    specs = seeded_inputs.serve_specs(SEED, n=args.requests, rate_per_s=rate)
-    log(f"generating {len(specs)} request boards (rate {rate:.0f}/s)")
-    payloads = [seeded_inputs.board_packed(SEED, s.board_id, s.rows, s.cols, s.p) for s in specs]
-    work = float(sum(s.rows * s.cols * s.generations for s in specs))
     results = [None] * len(specs)
-    T = args.t_block or BATCH_T
-
-    srv = gol.Server(hbm_budget_bytes=64 << 30, chunk_generations=args.chunk, t_block=T)
+    srv = gol.Server(hbm_budget_bytes=64 << 30, chunk_generations=args.chunk,
+                     t_block=args.t_block)
     # warm the pools: one small request
     w = payloads[0]
     srv.wait(srv.submit(w, specs[0].rows, specs[0].cols, 1), np.zeros_like(w))
@@ -498,64 +503,184 @@ def served(args, rate, cpu=True, plain=True):
             done[i] = info.done_s
             results[i] = out
 
-    log("continuous-batching server")
     th = threading.Thread(target=waiter)
     th.start()
     base = srv.now()
     t0 = time.perf_counter()
-    for i, s in enumerate(specs):
-        wait_until(t0, s.arrival_s)
-        tickets[i] = srv.submit(payloads[i], s.rows, s.cols, s.generations)
-        ready.release()
+    if saturate:
+        # four client threads submit interleaved slices of the requests at once
+        # (the server's calls are thread-safe); the waiter takes results in order
+        lock = threading.Lock()
+        submitted = [False] * len(specs)
+        nxt = [0]
+
+        def submitter(k):
+            for i in range(k, len(specs), SAT_SUBMITTERS):
+                s = specs[i]
+                tickets[i] = srv.submit(payloads[i], s.rows, s.cols, s.generations)
+                with lock:
+                    submitted[i] = True
+                    while nxt[0] < len(specs) and submitted[nxt[0]]:
+                        nxt[0] += 1
+                        ready.release()
+        subs = [threading.Thread(target=submitter, args=(k,)) for k in range(SAT_SUBMITTERS)]
+        for t in subs:
+            t.start()
+        for t in subs:
+            t.join()
+    else:
+        for i, s in enumerate(specs):
+            wait_until(t0, s.arrival_s)
+            tickets[i] = srv.submit(payloads[i], s.rows, s.cols, s.generations)
+            ready.release()
+    stats = {"submit_loop_s": time.perf_counter() - t0}
     th.join()
-    stats = srv.stats()
+    stats.update(srv.stats())
     srv.close()
-    arr = [base + s.arrival_s for s in specs]
+    return results, done, base, stats
+
+
+def stream_block(specs, done, base, stats, rate, work, args, saturate=False):
+    arr = [base + (0.0 if saturate else s.arrival_s) for s in specs]
     lat = [d - a for d, a in zip(done, arr)]
     span = max(done) - arr[0]
-    thr = work / span
-    blk = {"metric": "cell-updates/sec", "value": thr, "unit": "cell-updates/s", "steps": 1,
-           "timed_s": span, "dtype": "u32",
-           "config": {"workload": f"{len(specs)} requests, Poisson {rate:.0f}/s, sides "
-                                  "log-uniform [32, 8192], p U(0.05, 0.7), generations "
-                                  "U{1..10000}, 64 GiB budget", "requests": len(specs),
-                      "rate_per_s": rate, "chunk_generations": args.chunk, "t_block": T,
-                      "hbm_budget_bytes": 64 << 30, "seed": SEED, "cell_updates": work},
+    blk = {"value": work / span, "unit": "cell-updates/s", "timed_s": span,
+           "rate_per_s": None if saturate else rate,
            "latency_s": {"p50": nearest_rank(lat, 50), "p99": nearest_rank(lat, 99),
                          "max": max(lat)},
-           "offered_cell_updates_per_s": work / (specs[-1].arrival_s - specs[0].arrival_s),
-           "server": stats, "roofline": None}
+           "server": stats}
+    if not saturate:
+        blk["offered_cell_updates_per_s"] = work / (specs[-1].arrival_s - specs[0].arrival_s)
+    if stats.get("device_busy_s"):
+        blk["device_busy_frac"] = stats["device_busy_s"] / span
+    return blk
+
+
+def served(args, rate_rho=0.7, cpu=True, plain=True):
+    """The served configuration: 4096 requests (sides log-uniform [32, 8192],
+    p U(0.05, 0.7), generations U{1..10000}) from seed 1209.
+
+    capacity: the same 4096 boards as one batched schedule (tuned plan),
+    the throughput the served forms are measured against; saturated: every
+    request submitted at once; streams: open-loop Poisson arrivals at rho x
+    capacity / mean work per request for each rho in --rhos, the headline at
+    rho = rate_rho; plain: a FIFO server running one request at a time
+    (gol_step_packed per request) on the headline trace.  Latency =
+    completion - scheduled arrival."""
+    import torch
+    import paper_1209_4408_amd as gol
+    import seeded_inputs
+    specs = seeded_inputs.serve_specs(SEED, n=args.requests, rate_per_s=1.0)
+    log(f"generating {len(specs)} request boards")
+    payloads = [seeded_inputs.board_packed(SEED, s.board_id, s.rows, s.cols, s.p) for s in specs]
+    works = [s.rows * s.cols * s.generations for s in specs]
+    work = float(sum(works))
+    mean_work = work / len(specs)
+    # capacity: one batched schedule over the same boards
+    log("batched schedule over the served mix (capacity)")
+    sizes = [s.rows * ((s.cols + 63) // 64) for s in specs]
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    host = np.concatenate([p.reshape(-1) for p in payloads])
+    d_in = torch.from_numpy(host.view(np.int64)).cuda()
+    del host
+    d_out = torch.empty_like(d_in)
+    boards = [gol.BatchBoard(d_in[o:o + n].view(s.rows, -1), d_out[o:o + n].view(s.rows, -1),
+                             s.rows, s.cols, s.generations)
+              for s, o, n in zip(specs, offs[:-1], sizes)]
+    st = torch.cuda.Stream()
+    plan = gol.Plan(boards, t_block=args.t_block)
+    pcfg = plan.config()
+    with torch.cuda.stream(st):
+        wall_b, dev_b = timed_region(torch, lambda: plan.run(st), 2, 1, st)
+    plan.close()
+    # every request's result, for the served-equals-alone checks
+    alone = [d_out[o:o + n].cpu().numpy().view(np.uint64).reshape(s.rows, -1)
+             for s, o, n in zip(specs, offs[:-1], sizes)]
+    del boards, d_in, d_out
+    torch.cuda.empty_cache()
+    capacity = work * 2 / wall_b
+    blk = {"metric": "cell-updates/sec", "unit": "cell-updates/s", "steps": 1, "dtype": "u32",
+           "capacity_batched": {"value": capacity, "unit": "cell-updates/s", "steps": 2,
+                                "timed_s": wall_b, "plan": pcfg,
+                                "what": "the 4096 request boards as one batched schedule "
+                                        "(tuned plan, graph replay)"},
+           "config": {"workload": f"{len(specs)} requests, Poisson at {rate_rho} x the batched "
+                                  "capacity on the same boards, sides log-uniform [32, 8192], "
+                                  "p U(0.05, 0.7), generations U{1..10000}, 64 GiB budget",
+                      "requests": len(specs), "chunk_generations": args.chunk or "auto",
+                      "t_block": args.t_block or "tuned", "hbm_budget_bytes": 64 << 30,
+                      "seed": SEED, "cell_updates": work}}
+
+    def check(results):
+        return sum(0 if np.array_equal(r.reshape(a.shape), a) else 1
+                   for r, a in zip(results, alone))
+    rhos = sorted({float(r) for r in args.rhos.split(",") if r} | {rate_rho})
+    sweep = {}
+    head = None
+    for rho in rhos:
+        rate = rho * capacity / mean_work
+        sp = seeded_inputs.serve_specs(SEED, n=args.requests, rate_per_s=rate)
+        log(f"served stream at rho {rho}: {rate:.0f} requests/s")
+        res, done, base, stats = serve_stream(gol, sp, payloads, rate, args)
+        b = stream_block(sp, done, base, stats, rate, work, args)
+        b["mismatches_vs_batched"] = check(res)
+        sweep[f"{rho:g}"] = b
+        if rho == rate_rho:
+            head = (sp, b)
+    blk["rho_sweep"] = sweep
+    # after the streams, so the library's pinned staging pool is warm as in a
+    # long-running server
+    log("saturated server (all requests at once)")
+    res, done, base, stats = serve_stream(gol, specs, payloads, 0.0, args, saturate=True)
+    sat = stream_block(specs, done, base, stats, None, work, args, saturate=True)
+    sat["mismatches_vs_batched"] = check(res)
+    sat["over_capacity"] = sat["value"] / capacity
+    sat["submitters"] = SAT_SUBMITTERS
+    if stats.get("device_busy_s"):
+        sat["device_busy_rate"] = work / stats["device_busy_s"]
+        sat["device_busy_rate_over_capacity"] = sat["device_busy_rate"] / capacity
+    blk["saturated"] = sat
+    sp, hb = head
+    blk["value"] = hb["value"]
+    blk["timed_s"] = hb["timed_s"]
+    blk["latency_s"] = hb["latency_s"]
+    blk["rate_per_s"] = hb["rate_per_s"]
+    blk["served_equals_alone"] = all(b["mismatches_vs_batched"] == 0 for b in sweep.values()) \
+        and sat["mismatches_vs_batched"] == 0
+    stats = hb["server"]
+    blk["roofline"] = None
     if stats.get("device_busy_s"):
         blk["roofline"] = alu_roofline(stats["cell_updates"], stats["device_busy_s"],
-                                       f"k_batch_pass<{T}, *>", launches=stats["launches"],
+                                       f"k_batch_pass<{stats['t_block']}, *>",
+                                       launches=stats["launches"],
                                        note="algorithmic ops of every chunk over the chunks' "
                                             "device time (first to last launch of each)")
-    n_plain = min(len(specs), args.plain_requests) if plain else 0
+    n_plain = min(len(sp), args.plain_requests) if plain else 0
     if n_plain > 0:
         log(f"plain one-at-a-time server on the first {n_plain} requests")
-        st = torch.cuda.current_stream()
+        stq = torch.cuda.current_stream()
         lat_p = []
         t0 = time.perf_counter()
         mism = 0
         for i in range(n_plain):
-            s = specs[i]
+            s = sp[i]
             wait_until(t0, s.arrival_s)
-            d_in = torch.from_numpy(payloads[i].view(np.int64)).cuda()
-            d_out = gol.step_packed(d_in, s.rows, s.cols, s.generations)
-            res = d_out.cpu().numpy().view(np.uint64)
-            st.synchronize()
+            d_i = torch.from_numpy(payloads[i].view(np.int64)).cuda()
+            d_o = gol.step_packed(d_i, s.rows, s.cols, s.generations)
+            r = d_o.cpu().numpy().view(np.uint64)
+            stq.synchronize()
             lat_p.append(time.perf_counter() - t0 - s.arrival_s)
-            if not np.array_equal(res, results[i]):
+            if not np.array_equal(r.reshape(alone[i].shape), alone[i]):
                 mism += 1
-        span_p = time.perf_counter() - t0 - specs[0].arrival_s
-        work_p = float(sum(s.rows * s.cols * s.generations for s in specs[:n_plain]))
+        span_p = time.perf_counter() - t0 - sp[0].arrival_s
+        work_p = float(sum(works[:n_plain]))
         blk["plain"] = {"value": work_p / span_p, "unit": "cell-updates/s", "requests": n_plain,
                         "timed_s": span_p,
                         "latency_s": {"p50": nearest_rank(lat_p, 50),
                                       "p99": nearest_rank(lat_p, 99)},
+                        "mismatches_vs_batched": mism,
                         "what": "FIFO, one request at a time, gol_step_packed per request"}
-        blk["served_equals_alone"] = (mism == 0)
-        blk["speedup_vs_plain"] = thr / blk["plain"]["value"]
+        blk["speedup_vs_plain"] = blk["value"] / blk["plain"]["value"]
     if cpu and not args.no_cpu:
         log("cpu baseline (oracle) on a sample of the requests")
         blk["cpu_baseline"] = cpu_baseline_boards(specs, SEED, what="requests")
@@ -567,21 +692,16 @@ def default_line(args):
     import torch
     blocks = {}
     log("== c3: 65536^2 x 200")
-    c3 = single_board(args, 65536, 65536, 200, 0.5, args.config_c3, compare_t1=True)
+    # the oracle on 20 of the 200 generations (its rate does not depend on the
+    # generation count, so the sample scales linearly)
+    c3 = single_board(args, 65536, 65536, 200, 0.5, args.config_c3, compare_t1=True,
+                      cpu_gens=args.c3_cpu_gens)
     log("== c2: 16384^2 x 1000")
     blocks["c2"] = single_board(args, 16384, 16384, 1000, 0.3, args.config_c2)
     log("== c4: 4096 boards")
     blocks["c4"] = batched(args)
-    # the served stream's arrival rate: 0.7 of the batched capacity just measured,
-    # in requests per second of the stream's own mean work
-    import seeded_inputs
-    sp = seeded_inputs.serve_specs(SEED, n=args.requests, rate_per_s=1.0)
-    mean_work = float(np.mean([s.rows * s.cols * s.generations for s in sp]))
-    rate = args.rate or 0.7 * blocks["c4"]["value"] / mean_work
-    log(f"== c5: Poisson stream at {rate:.0f} requests/s")
-    blocks["c5"] = served(args, rate)
-    blocks["c5"]["rate_rule"] = ("0.7 x the batched block's cell-updates/s / the stream's mean "
-                                 "work per request" if not args.rate else "--rate")
+    log("== c5: served stream")
+    blocks["c5"] = served(args)
     log("== c1: host API")
     blocks["c1"] = host_api(args)
     torch.cuda.synchronize()
@@ -967,13 +1087,12 @@ def main():
                     choices=["all", "c1", "c2", "c3", "c4", "c5", "copy", "pop", "bounded",
                              "strip", "decomp", "valu"])
     ap.add_argument("--requests", type=int, default=4096)
-    ap.add_argument("--rate", type=float, default=0.0,
-                    help="Poisson arrival rate of the served stream; 0 = 0.7 of the batched "
-                         "capacity measured in the same run (default line), or 2700/s "
-                         "(--workload c5)")
-    ap.add_argument("--rates", default="",
-                    help="--workload c5: comma-separated arrival rates to sweep")
-    ap.add_argument("--chunk", type=int, default=240)
+    ap.add_argument("--rhos", default="0.3,0.5,0.9",
+                    help="served stream: arrival rates to sweep, as fractions of the batched "
+                         "capacity on the same boards (0.7, the headline, always runs)")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="served stream: generations per chunk (0 = the server's automatic "
+                         "length)")
     ap.add_argument("--plain-requests", type=int, default=4096)
     ap.add_argument("--boards", type=int, default=4096)
     ap.add_argument("--t-block", type=int, default=0)
@@ -987,6 +1106,9 @@ def main():
                          "(layout 1 = one band per wave, 2 = paired bands) of a single-board "
                          "workload; skips the autotuner")
     ap.add_argument("--config-c3", default="", help="--config for the default line's c3 board")
+    ap.add_argument("--c3-cpu-gens", type=int, default=20,
+                    help="generations of the 65536^2 board the oracle times (0 = a budget of "
+                         "about 15 s)")
     ap.add_argument("--config-c2", default="", help="--config for the default line's c2 board")
     ap.add_argument("--sweep", action="store_true",
                     help="time T in {2,4,8,16} x band heights for the single-board workload")
@@ -1015,13 +1137,7 @@ def main():
     elif args.workload == "c1":
         line = single_line(args, host_api(args))
     elif args.workload == "c5":
-        rates = [float(r) for r in args.rates.split(",") if r] or [args.rate or 2700.0]
-        for rate in rates:
-            line = single_line(args, served(args, rate, plain=not args.no_plain))
-            if len(rates) > 1:
-                print(json.dumps(line), flush=True)
-        if len(rates) > 1:
-            return
+        line = single_line(args, served(args, plain=not args.no_plain))
     elif args.workload == "copy":
         copy_calibration(args)
         return

@@ -253,8 +253,23 @@ int gol_batch_run(const gol_board* boards, int64_t n, void* stream);
  * the first run and replayed afterwards).  The plan owns its scratch.
  */
 typedef struct gol_plan gol_plan;
-/* t_block: generations per pass, 0 = default (16), else 1, 2, 4, 8, 12 or 16. */
+/* t_block: generations per pass, 0 = tuned, else 1, 2, 4, 8, 12 or 16; the
+ * band height is tuned (see gol_plan_create_cfg). */
 int gol_plan_create(const gol_board* boards, int64_t n, int t_block, gol_plan** out);
+/*
+ * gol_plan_create with the band height too: config->t_block and
+ * config->band_rows (rows per tile band, 1 .. 65535); prefetch and layout
+ * must be 0.  A field of 0 is tuned: creation times the candidate schedules
+ * (t_block 8, 12 or 16; band_rows 48, 64, 96 or 128) of these boards on
+ * zeroed scratch boards of the same sizes, allocated and freed inside the call
+ * (of every k-th board when they would take more than 1 GiB; the defaults,
+ * 16 and 96, when the device has no room), and keeps the fastest.  Creation
+ * is synchronous; the buffers of `boards` are not touched.
+ */
+int gol_plan_create_cfg(const gol_board* boards, int64_t n, const gol_pass_config* config,
+                        gol_plan** out);
+/* The plan's generations per pass and band height (other fields 0). */
+int gol_plan_config(const gol_plan* plan, gol_pass_config* out);
 int gol_plan_run(gol_plan* plan, void* stream);
 /* Describes the plan: waves per level 0, levels, total cell updates. */
 int gol_plan_info(const gol_plan* plan, int64_t* waves, int64_t* levels, double* cell_updates);
@@ -269,10 +284,20 @@ int gol_plan_destroy(gol_plan* plan);
  */
 typedef struct gol_serve_config {
   uint64_t hbm_budget_bytes;   /* device bytes for resident boards */
-  int32_t chunk_generations;   /* generations per tick (>= 1) */
+  int32_t chunk_generations;   /* generations per tick (>= 1), or 0: automatic -- each
+                                  tick runs the whole passes that take the resident boards
+                                  about 3 ms of device time at the rate measured on earlier
+                                  ticks (15 passes until one has completed) */
   int32_t device;              /* HIP device ordinal */
   int32_t max_resident;        /* cap on resident boards (0 = no cap) */
-  int32_t t_block;             /* generations per pass: 0 = default (16), 1, 2, 4, 8, 12, 16 */
+  int32_t t_block;             /* generations per pass: 1, 2, 4, 8, 12, 16, or 0: tuned at
+                                  creation together with the band height of the tiles (8, 12
+                                  or 16 x 64, 96 or 128 rows, whichever runs a stand-in
+                                  resident set fastest: square boards of 512 to 8192 a side,
+                                  the same cells at each size, 48 generations; with t_block
+                                  given only the band height is timed).  A chunk whose tiles
+                                  give fewer than two waves per SIMD halves the band height
+                                  (not below 32 rows or t_block) until they do. */
 } gol_serve_config;
 
 typedef struct gol_server gol_server;
@@ -312,6 +337,10 @@ typedef struct {
   double mean_resident;    /* boards per chunk, averaged over chunks */
   int64_t resident_bytes;  /* device bytes of resident boards now */
   int64_t peak_resident_bytes; /* largest value of resident_bytes (never above the budget) */
+  int64_t t_block;         /* generations per pass of every chunk (given or tuned) */
+  int64_t last_chunk_generations; /* generations of the last chunk queued (at most) */
+  int64_t last_band_rows;  /* band height of the last chunk's tiles */
+  int64_t busy_band_rows;  /* band height of a chunk with many tiles (given or tuned) */
 } gol_serve_stats;
 int gol_serve_get_stats(const gol_server* srv, gol_serve_stats* out);
 int gol_serve_destroy(gol_server* srv);

@@ -40,12 +40,31 @@ int gol_debug_plan_tables(const int64_t* rows, const int64_t* cols, const int64_
                           int64_t* nlevels);
 
 /*
+ * The same tables for a served chunk: each board tiled on its own
+ * (consecutive bands of one narrow strip share a wave; no wave holds two
+ * boards) and the boards' waves assembled in pass-count order, as a server's
+ * chunk is built.  band_rows 0 = the band height a server whose busy
+ * height is 96 picks for these boards on a 1024-SIMD device (96, halved
+ * while the tiles give fewer than two waves per SIMD, not below 32 rows or
+ * t_block); *band_used (may be NULL) receives the height used.
+ */
+int gol_debug_chunk_plan_tables(const int64_t* rows, const int64_t* cols, const int64_t* gens,
+                                int64_t n, int t_block, int band_rows, void* segs,
+                                int64_t cap_segs, void* items, int64_t cap_items,
+                                int32_t* levels, int64_t cap_levels, int32_t* starts,
+                                int32_t* late_begin, int64_t* nsegs, int64_t* nitems,
+                                int64_t* nlevels, int32_t* band_used);
+
+/*
  * A server whose "device" is host memory, for testing the serving scheduler
  * (admission by budget, chunking, the buffer that holds each board's state,
  * retirement, cancellation, failure handling) without a GPU.  Every queued
- * operation completes at once.  Its stand-in for advancing a board by g
- * generations adds g (mod 2^64) to every word; it computes nothing of the Life
- * rule.  fail_at_chunk > 0 makes the fail_at_chunk-th chunk report
+ * operation completes at once.  It replays each chunk's schedule level by
+ * level and tile by tile as the device would; its stand-in for a pass of t
+ * generations adds t (mod 2^32) to every 32-bit word of the tile, so a board
+ * advanced by g generations has g added to each of its 32-bit words; it
+ * computes nothing of the Life rule.  A pass shorter than t_block in a level
+ * launched without the short-pass mask fails the chunk (GOL_EDEVICE).  fail_at_chunk > 0 makes the fail_at_chunk-th chunk report
  * GOL_EDEVICE (the server then fails every unfinished request).  Use the
  * gol_serve_* calls on the result; cfg->device is ignored.
  */

@@ -16,7 +16,9 @@ from typing import Iterable, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgol.so")
+# GOL_LIB names another build of the same library (the host-sanitizer builds
+# of build.py for CPU test runs); by default the in-tree libgol.so.
+LIB_PATH = os.environ.get("GOL_LIB") or os.path.join(_HERE, "libgol.so")
 
 GOL_OK = 0
 GOL_EINVAL = -1
@@ -57,7 +59,9 @@ class ServeStats(ctypes.Structure):
                 ("plan_host_s", ctypes.c_double), ("device_busy_s", ctypes.c_double),
                 ("cell_updates", ctypes.c_double), ("max_resident", ctypes.c_int64),
                 ("mean_resident", ctypes.c_double), ("resident_bytes", ctypes.c_int64),
-                ("peak_resident_bytes", ctypes.c_int64)]
+                ("peak_resident_bytes", ctypes.c_int64), ("t_block", ctypes.c_int64),
+                ("last_chunk_generations", ctypes.c_int64), ("last_band_rows", ctypes.c_int64),
+                ("busy_band_rows", ctypes.c_int64)]
 
 
 class RequestInfo(ctypes.Structure):
@@ -102,6 +106,9 @@ def lib():
             "gol_unpack": (c_int, [vp, i64, i64, vp, vp]),
             "gol_batch_run": (c_int, [vp, i64, vp]),
             "gol_plan_create": (c_int, [vp, i64, c_int, ctypes.POINTER(vp)]),
+            "gol_plan_create_cfg": (c_int, [vp, i64, ctypes.POINTER(PassConfig),
+                                            ctypes.POINTER(vp)]),
+            "gol_plan_config": (c_int, [vp, ctypes.POINTER(PassConfig)]),
             "gol_plan_run": (c_int, [vp, vp]),
             "gol_plan_info": (c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                       ctypes.POINTER(ctypes.c_double)]),
@@ -123,6 +130,12 @@ def lib():
                                               i64, vp, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(i64), ctypes.POINTER(i64),
                                               ctypes.POINTER(i64)]),
+            "gol_debug_chunk_plan_tables": (c_int, [vp, vp, vp, i64, c_int, c_int, vp, i64, vp,
+                                                    i64, vp, i64, vp,
+                                                    ctypes.POINTER(ctypes.c_int32),
+                                                    ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                                    ctypes.POINTER(i64),
+                                                    ctypes.POINTER(ctypes.c_int32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -400,13 +413,21 @@ def batch_run(boards: Sequence[BatchBoard], stream=None) -> None:
 class Plan:
     """A batch schedule built once and replayed (HIP graph) on the same buffers."""
 
-    def __init__(self, boards: Sequence[BatchBoard], t_block: int = 0):
+    def __init__(self, boards: Sequence[BatchBoard], t_block: int = 0, band_rows: int = 0):
+        """t_block / band_rows 0: tuned at creation (gol_plan_create_cfg)."""
         self._boards = list(boards)  # keep the tensors alive
         arr = _board_array(self._boards)
         h = ctypes.c_void_p()
-        _check(lib().gol_plan_create(ctypes.cast(arr, ctypes.c_void_p), len(self._boards),
-                                     int(t_block), ctypes.byref(h)))
+        c = PassConfig(t_block=int(t_block), band_rows=int(band_rows))
+        _check(lib().gol_plan_create_cfg(ctypes.cast(arr, ctypes.c_void_p), len(self._boards),
+                                         ctypes.byref(c), ctypes.byref(h)))
         self._h = h
+
+    def config(self) -> dict:
+        """The plan's generations per pass and band height (tuned or given)."""
+        c = PassConfig()
+        _check(lib().gol_plan_config(self._h, ctypes.byref(c)))
+        return {"t_block": c.t_block, "band_rows": c.band_rows}
 
     def run(self, stream=None) -> None:
         _check(lib().gol_plan_run(self._h, _stream_handle(stream)))
@@ -438,7 +459,7 @@ class Server:
     GPU (gol_debug_serve_create_host): for testing the scheduling policy; it
     does not compute the Life rule."""
 
-    def __init__(self, hbm_budget_bytes: int = 64 << 30, chunk_generations: int = 240,
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, chunk_generations: int = 0,
                  device: int = 0, max_resident: int = 0, t_block: int = 0,
                  host_executor: bool = False, fail_at_chunk: int = 0):
         cfg = ServeConfig(hbm_budget_bytes, chunk_generations, device, max_resident, t_block)
@@ -532,29 +553,40 @@ WAVEITEM_DTYPE = np.dtype([("seg_begin", "<i4"), ("nseg", "<i2"), ("h", "<u2"), 
 
 
 def plan_tables(rows: Iterable[int], cols: Iterable[int], generations: Iterable[int],
-                t_block: int = 8, band_rows: int = 64):
+                t_block: int = 8, band_rows: int = 64, chunk: bool = False):
     """The batch schedule the library would build for these boards (host only).
 
     Returns (segs, items, levels, late_begin, starts): levels[L] = (early, late)
     wave counts of level L, which launches items[:early] and
     items[late_begin:late_begin + late]; starts[b] = level of board b's first
-    pass."""
+    pass.  chunk=True: the schedule of a served chunk (each board tiled on
+    its own; band_rows 0 = the server's model choice), and a sixth element,
+    the band height used."""
     r = np.ascontiguousarray(list(rows), dtype=np.int64)
     c = np.ascontiguousarray(list(cols), dtype=np.int64)
     g = np.ascontiguousarray(list(generations), dtype=np.int64)
     ns, ni, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    lb = ctypes.c_int32()
-    _check(lib().gol_debug_plan_tables(r.ctypes.data, c.ctypes.data, g.ctypes.data, len(r),
-                                       t_block, band_rows, None, 0, None, 0, None, 0, None,
-                                       ctypes.byref(lb), ctypes.byref(ns), ctypes.byref(ni),
-                                       ctypes.byref(nl)))
+    lb, band = ctypes.c_int32(), ctypes.c_int32()
+
+    def call(segs, items, levels, starts):
+        args = [r.ctypes.data, c.ctypes.data, g.ctypes.data, len(r), t_block, band_rows,
+                segs.ctypes.data if segs is not None else None, 0 if segs is None else len(segs),
+                items.ctypes.data if items is not None else None,
+                0 if items is None else len(items),
+                levels.ctypes.data if levels is not None else None,
+                0 if levels is None else len(levels),
+                starts.ctypes.data if starts is not None else None, ctypes.byref(lb),
+                ctypes.byref(ns), ctypes.byref(ni), ctypes.byref(nl)]
+        if chunk:
+            _check(lib().gol_debug_chunk_plan_tables(*args, ctypes.byref(band)))
+        else:
+            _check(lib().gol_debug_plan_tables(*args))
+    call(None, None, None, None)
     segs = np.zeros(ns.value, dtype=SEGMENT_DTYPE)
     items = np.zeros(ni.value, dtype=WAVEITEM_DTYPE)
     levels = np.zeros((nl.value, 2), dtype=np.int32)
     starts = np.zeros(len(r), dtype=np.int32)
-    _check(lib().gol_debug_plan_tables(r.ctypes.data, c.ctypes.data, g.ctypes.data, len(r),
-                                       t_block, band_rows, segs.ctypes.data, len(segs),
-                                       items.ctypes.data, len(items), levels.ctypes.data,
-                                       len(levels), starts.ctypes.data, ctypes.byref(lb),
-                                       ctypes.byref(ns), ctypes.byref(ni), ctypes.byref(nl)))
+    call(segs, items, levels, starts)
+    if chunk:
+        return segs, items, levels, int(lb.value), starts, int(band.value)
     return segs, items, levels, int(lb.value), starts

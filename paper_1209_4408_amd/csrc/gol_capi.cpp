@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <map>
 #include <cstdarg>
@@ -143,6 +144,13 @@ struct Deferred {
 };
 static std::vector<Deferred> g_deferred;
 
+// Blocks of a class up to kSlabMaxClass are carved from one hipHostMalloc of
+// eight blocks (at least 1 MiB), so a burst of requests pins memory in a
+// few large calls instead of one call per block (page-locking is the slow
+// part of hipHostMalloc).  Blocks never return to the system.
+constexpr size_t kSlabMaxClass = (size_t)8 << 20;
+constexpr size_t kSlabBlocks = 8;
+
 void* pinned_get(size_t bytes, size_t* cls_out) {
   size_t cls = 4096;
   while (cls < bytes) cls <<= 1;
@@ -156,12 +164,24 @@ void* pinned_get(size_t bytes, size_t* cls_out) {
       return p;
     }
   }
+  const size_t n = cls <= kSlabMaxClass ? std::max(kSlabBlocks, ((size_t)1 << 20) / cls) : 1;
   void* p = nullptr;
-  if (hipHostMalloc(&p, cls, hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc(&p, cls * n, hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     return nullptr;
   }
+  if (n > 1) {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto& v = g_pin_free[cls];
+    for (size_t i = 1; i < n; ++i) v.push_back((char*)p + i * cls);
+  }
   return p;
+}
+
+void pinned_put(void* p, size_t cls) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free[cls].push_back(p);
 }
 
 static hipError_t event_get(hipEvent_t* ev) {
@@ -242,8 +262,6 @@ static bool resident_auto(int64_t R, int64_t C) {
 }
 int default_batch_T() { return 16; }
 
-// Band height of batched schedules (tiles of many boards share a level).
-constexpr int kBatchBandRows = 96;
 
 // SIMDs of the current device (4 per compute unit), cached per device.
 int simd_count() {
@@ -777,6 +795,127 @@ int batch_run(const gol_board* boards, int64_t n, hipStream_t st, int T) {
   return rc;
 }
 
+// Candidate schedules of a batch, timed on zeroed scratch boards of the
+// same sizes (a pass's run time does not depend on the cells): for each
+// (T, band height) the schedule runs once to warm up and once timed with
+// events on a library stream; the fastest wins.  The scratch (input, output
+// and ping-pong board per board) is freed before returning.
+int tune_batch(const std::vector<BoardReq>& boards, const std::vector<int>& Ts,
+               const std::vector<int>& bands, int* T_out, int* band_out, double* secs_out) {
+  size_t words = 0;
+  std::vector<size_t> off(boards.size(), 0);
+  for (size_t b = 0; b < boards.size(); ++b) {
+    off[b] = words;
+    words += (size_t)(boards[b].rows * ((boards[b].cols + 63) / 64));
+  }
+  *T_out = Ts.empty() ? default_batch_T() : Ts[0];
+  *band_out = bands.empty() ? kBatchBandRows : bands[0];
+  if (secs_out) *secs_out = 0.0;
+  if (words == 0 || Ts.empty() || bands.empty()) return GOL_OK;
+  HostSlot slot;
+  int rc = acquire_slot(&slot);
+  if (rc) return rc;
+  hipStream_t st = slot.st;
+  SideStream side;
+  rc = side.open();
+  void* buf = nullptr;
+  if (!rc) rc = scratch_alloc(&buf, 3 * words * 8, st);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipSuccess;
+  if (!rc) {
+    e = launch_fill_u32((uint32_t*)buf, (int64_t)(2 * words), 0u, st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+  }
+  double best = 1e300;
+  std::vector<gol_board> gb(boards.size());
+  uint64_t* in = (uint64_t*)buf;
+  for (size_t b = 0; b < boards.size(); ++b)
+    gb[b] = gol_board{in + off[b], in + words + off[b], boards[b].rows, boards[b].cols,
+                      boards[b].generations};
+  for (int T : Ts) {
+    for (int band : bands) {
+      if (rc || e != hipSuccess) break;
+      DevicePlan P;
+      rc = plan_boards(gb.data(), (int64_t)gb.size(), T, band, P);
+      if (rc) break;
+      P.d_scratch = in + 2 * words;
+      fill_board_descs(P);
+      size_t ob, os, oi;
+      const size_t mb = meta_bytes(P, &ob, &os, &oi);
+      std::vector<char> host(mb);
+      fill_meta_host(P, host.data(), ob, os, oi);
+      void* meta = nullptr;
+      rc = scratch_alloc(&meta, mb, st);
+      if (rc) break;
+      e = hipMemcpyAsync(meta, host.data(), mb, hipMemcpyHostToDevice, st);
+      P.d_boards = (BoardDesc*)((char*)meta + ob);
+      P.d_segs = (Segment*)((char*)meta + os);
+      P.d_items = (WaveItem*)((char*)meta + oi);
+      if (e == hipSuccess) e = enqueue_plan(P, st, side.st, side.fork, side.join);
+      if (e == hipSuccess) e = hipEventRecord(e0, st);
+      if (e == hipSuccess) e = enqueue_plan(P, st, side.st, side.fork, side.join);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      scratch_free(meta, st);
+      if (e == hipSuccess && ms < best) {
+        best = ms;
+        *T_out = T;
+        *band_out = band;
+      }
+    }
+  }
+  if (buf) scratch_free(buf, st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  hipError_t es = hipStreamSynchronize(st);
+  release_slot(slot);
+  if (rc) return rc;
+  if (e == hipSuccess) e = es;
+  if (e != hipSuccess) return hip_error(e, "batch tuning");
+  if (secs_out) *secs_out = best * 1e-3;
+  return GOL_OK;
+}
+
+// The automatic fields of a plan's configuration (*T == 0: T in 8, 12, 16;
+// *band == 0: 48, 64, 96 or 128 rows), timed on scratch copies of the boards
+// (or, above kTuneMaxBytes of them, of every k-th board).  Boards that are
+// invalid are left for plan_boards to reject.
+constexpr size_t kTuneMaxBytes = (size_t)1 << 30;
+static int tune_plan(const gol_board* boards, int64_t n, int* T, int* band) {
+  std::vector<int> Ts = *T ? std::vector<int>{*T} : std::vector<int>{8, 12, 16};
+  std::vector<int> bands =
+      *band ? std::vector<int>{*band} : std::vector<int>{48, 64, 96, 128};
+  if (!*T) *T = default_batch_T();
+  if (!*band) *band = kBatchBandRows;
+  if (n <= 0 || !boards) return GOL_OK;
+  double bytes = 0.0;
+  for (int64_t b = 0; b < n; ++b) {
+    const gol_board& g = boards[b];
+    if (check_board(g.rows, g.cols, g.generations)) {
+      clear_error();
+      return GOL_OK;
+    }
+    bytes += 3.0 * (double)g.rows * (double)((g.cols + 63) / 64) * 8.0;
+  }
+  const int64_t k = std::max<int64_t>(1, (int64_t)std::ceil(bytes / (double)kTuneMaxBytes));
+  std::vector<BoardReq> req;
+  for (int64_t b = 0; b < n; b += k)
+    req.push_back(BoardReq{boards[b].rows, boards[b].cols, boards[b].generations});
+  int t = *T, h = *band;
+  const int rc = tune_batch(req, Ts, bands, &t, &h, nullptr);
+  if (rc == GOL_ENOMEM) {  // no room to time: keep the defaults
+    clear_error();
+    return GOL_OK;
+  }
+  if (rc) return rc;
+  *T = t;
+  *band = h;
+  return GOL_OK;
+}
+
 }  // namespace gol
 
 // ---------------------------------------------------------------------------
@@ -1017,12 +1156,34 @@ int gol_batch_run(const gol_board* boards, int64_t n, void* stream) {
 }
 
 int gol_plan_create(const gol_board* boards, int64_t n, int t_block, gol_plan** out) {
+  gol_pass_config c{};
+  c.t_block = t_block;
+  return gol_plan_create_cfg(boards, n, &c, out);
+}
+
+int gol_plan_create_cfg(const gol_board* boards, int64_t n, const gol_pass_config* config,
+                        gol_plan** out) {
   if (!out) return set_error(GOL_EINVAL, "null output pointer");
   *out = nullptr;
   gol_plan* p = nullptr;
   try {
+    gol_pass_config cfg{};
+    if (config) cfg = *config;
+    if (cfg.t_block < 0 || cfg.band_rows < 0 || cfg.band_rows > 65535 || cfg.prefetch != 0 ||
+        cfg.layout != 0)
+      return set_error(GOL_EINVAL,
+                       "a batch plan takes t_block (0, 1, 2, 4, 8, 12, 16) and band_rows "
+                       "(0 .. 65535); prefetch and layout must be 0");
+    if (cfg.t_block != 0 && !valid_T(cfg.t_block))
+      return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8, 12 or 16 (got %d)",
+                       cfg.t_block);
+    int T = cfg.t_block, band = cfg.band_rows;
+    if (T == 0 || band == 0) {
+      int rc = tune_plan(boards, n, &T, &band);
+      if (rc) return rc;
+    }
     p = new gol_plan();
-    int rc = plan_boards(boards, n, t_block, 0, p->P);
+    int rc = plan_boards(boards, n, T, band, p->P);
     if (rc) {
       delete p;
       return rc;
@@ -1109,6 +1270,14 @@ int gol_plan_run(gol_plan* p, void* stream) {
   return e == hipSuccess ? GOL_OK : hip_error(e, "hipGraphLaunch");
 }
 
+int gol_plan_config(const gol_plan* p, gol_pass_config* out) {
+  if (!p || !out) return set_error(GOL_EINVAL, "null argument");
+  *out = gol_pass_config{};
+  out->t_block = p->P.hp.T;
+  out->band_rows = p->P.hp.band_rows;
+  return GOL_OK;
+}
+
 int gol_plan_info(const gol_plan* p, int64_t* waves, int64_t* levels, double* cell_updates) {
   if (!p) return set_error(GOL_EINVAL, "null plan");
   if (waves) *waves = p->P.hp.level_items.empty() ? 0 : p->P.hp.level_items[0];
@@ -1152,6 +1321,28 @@ int gol_set_allocator(gol_alloc_fn alloc, gol_free_fn free_fn, void* ctx) {
 // segments and cap_items waves; returns their counts, the level sizes (up to
 // cap_levels pairs), the late group's first wave and each board's first
 // level.  Returns GOL_EINVAL on invalid boards.
+static void copy_plan_tables(const HostPlan& hp, void* segs, int64_t cap_segs, void* items,
+                             int64_t cap_items, int32_t* levels, int64_t cap_levels,
+                             int32_t* starts, int32_t* late_begin, int64_t* nsegs,
+                             int64_t* nitems, int64_t* nlevels) {
+  if (nsegs) *nsegs = (int64_t)hp.segs.size();
+  if (nitems) *nitems = (int64_t)hp.items.size();
+  if (nlevels) *nlevels = (int64_t)hp.level_items.size();
+  if (segs)
+    memcpy(segs, hp.segs.data(),
+           std::min<size_t>(hp.segs.size(), (size_t)cap_segs) * sizeof(Segment));
+  if (items)
+    memcpy(items, hp.items.data(),
+           std::min<size_t>(hp.items.size(), (size_t)cap_items) * sizeof(WaveItem));
+  if (levels)
+    for (size_t L = 0; L < std::min<size_t>(hp.level_items.size(), (size_t)cap_levels); ++L) {
+      levels[2 * L] = hp.level_early[L];
+      levels[2 * L + 1] = hp.level_late[L];
+    }
+  if (starts) memcpy(starts, hp.start.data(), hp.start.size() * sizeof(int32_t));
+  if (late_begin) *late_begin = hp.late_begin;
+}
+
 int gol_debug_plan_tables(const int64_t* rows, const int64_t* cols, const int64_t* gens, int64_t n,
                           int t_block, int band_rows, void* segs, int64_t cap_segs, void* items,
                           int64_t cap_items, int32_t* levels, int64_t cap_levels,
@@ -1166,22 +1357,44 @@ int gol_debug_plan_tables(const int64_t* rows, const int64_t* cols, const int64_
     if (t_block == 0) t_block = default_batch_T();
     if (!build_plan(req, t_block, band_rows > 0 ? band_rows : 64, hp, err))
       return set_error(GOL_EINVAL, "%s", err.c_str());
-    if (nsegs) *nsegs = (int64_t)hp.segs.size();
-    if (nitems) *nitems = (int64_t)hp.items.size();
-    if (nlevels) *nlevels = (int64_t)hp.level_items.size();
-    if (segs)
-      memcpy(segs, hp.segs.data(),
-             std::min<size_t>(hp.segs.size(), (size_t)cap_segs) * sizeof(Segment));
-    if (items)
-      memcpy(items, hp.items.data(),
-             std::min<size_t>(hp.items.size(), (size_t)cap_items) * sizeof(WaveItem));
-    if (levels)
-      for (size_t L = 0; L < std::min<size_t>(hp.level_items.size(), (size_t)cap_levels); ++L) {
-        levels[2 * L] = hp.level_early[L];
-        levels[2 * L + 1] = hp.level_late[L];
-      }
-    if (starts) memcpy(starts, hp.start.data(), hp.start.size() * sizeof(int32_t));
-    if (late_begin) *late_begin = hp.late_begin;
+    copy_plan_tables(hp, segs, cap_segs, items, cap_items, levels, cap_levels, starts,
+                     late_begin, nsegs, nitems, nlevels);
+    return GOL_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(GOL_ENOMEM, "host allocation failed");
+  }
+}
+
+int gol_debug_chunk_plan_tables(const int64_t* rows, const int64_t* cols, const int64_t* gens,
+                                int64_t n, int t_block, int band_rows, void* segs,
+                                int64_t cap_segs, void* items, int64_t cap_items,
+                                int32_t* levels, int64_t cap_levels, int32_t* starts,
+                                int32_t* late_begin, int64_t* nsegs, int64_t* nitems,
+                                int64_t* nlevels, int32_t* band_used) {
+  try {
+    if (n < 0 || (n > 0 && (!rows || !cols || !gens))) return set_error(GOL_EINVAL, "bad arrays");
+    if (t_block == 0) t_block = default_batch_T();
+    if (!valid_T(t_block)) return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8, 12 or 16");
+    std::vector<std::pair<int64_t, int64_t>> dims;
+    for (int64_t b = 0; b < n; ++b) {
+      const int rc = check_board(rows[b], cols[b], gens[b]);
+      if (rc) return rc;
+      dims.emplace_back(rows[b], cols[b]);
+    }
+    const int h = band_rows > 0 ? band_rows : chunk_band_rows(dims, t_block, 1024, kBatchBandRows);
+    if (h > 65535) return set_error(GOL_EINVAL, "band height out of range");
+    std::vector<BoardTiles> tiles((size_t)n);
+    std::vector<ChunkBoard> req((size_t)n);
+    for (int64_t b = 0; b < n; ++b) {
+      board_tiles(rows[b], cols[b], h, tiles[b]);
+      req[b] = ChunkBoard{&tiles[b], rows[b], cols[b], gens[b]};
+    }
+    HostPlan hp;
+    std::string err;
+    if (!build_chunk_plan(req, t_block, hp, err)) return set_error(GOL_EINVAL, "%s", err.c_str());
+    copy_plan_tables(hp, segs, cap_segs, items, cap_items, levels, cap_levels, starts,
+                     late_begin, nsegs, nitems, nlevels);
+    if (band_used) *band_used = h;
     return GOL_OK;
   } catch (const std::bad_alloc&) {
     return set_error(GOL_ENOMEM, "host allocation failed");

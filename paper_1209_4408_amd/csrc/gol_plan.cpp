@@ -174,6 +174,9 @@ static std::vector<ItemBuild> pack_waves(const std::vector<BoardReq>& boards,
         it.lanes += sg.nlanes;
         it.aligned = it.aligned && aligned;
         if (it.lanes > kWave - 3) open.erase(open.begin() + pick);
+        // only the last 64 open waves are ever searched: waves far behind
+        // them close, which keeps each erase short
+        if (open.size() > 512) open.erase(open.begin(), open.end() - 128);
       }
     }
   }
@@ -282,6 +285,186 @@ bool build_plan(const std::vector<BoardReq>& boards, int T, int band_rows, HostP
     for (size_t i = 0; i < cl; ++i) plan.lane_steps += (double)kWave * (bl[i].h + 2 * T);
   }
   return true;
+}
+
+
+void board_tiles(int64_t rows, int64_t cols, int band_rows, BoardTiles& out) {
+  out.band_rows = band_rows;
+  out.aligned = (cols % 32) == 0;
+  out.segs.clear();
+  out.waves.clear();
+  const int64_t D = dwords_per_row(cols);
+  const int64_t ns = (D + kStripDwords - 1) / kStripDwords;
+  const Split S = split(D, ns);
+  const int64_t nb = (rows + band_rows - 1) / band_rows;
+  const Split B = split(rows, nb);
+  // lanes of the widest strip: segments per wave when strips are narrow
+  const int64_t lanes = S.size(0) + 2;
+  const int64_t per = std::max<int64_t>(1, kWave / lanes);
+  out.segs.reserve((size_t)(ns * nb));
+  for (int64_t si = 0; si < ns; ++si) {
+    for (int64_t b0 = 0; b0 < nb; b0 += per) {
+      BoardTiles::Wave w;
+      w.seg_begin = (int32_t)out.segs.size();
+      w.nseg = 0;
+      w.h = 0;
+      int lane = 0;
+      for (int64_t bi = b0; bi < std::min(nb, b0 + per); ++bi) {
+        Segment sg;
+        sg.board = 0;
+        sg.p0 = (int32_t)(S.start(si) - 1);
+        sg.r0 = (int32_t)B.start(bi);
+        sg.h = (uint16_t)B.size(bi);
+        sg.lane0 = (uint8_t)lane;
+        sg.nlanes = (uint8_t)(S.size(si) + 2);
+        lane += sg.nlanes;
+        w.h = std::max<uint16_t>(w.h, sg.h);
+        w.nseg += 1;
+        out.segs.push_back(sg);
+      }
+      out.waves.push_back(w);
+    }
+  }
+}
+
+bool build_chunk_plan(const std::vector<ChunkBoard>& boards, int T, HostPlan& plan,
+                      std::string& err) {
+  if (!valid_T(T)) {
+    err = "generations per pass must be 1, 2, 4, 8, 12 or 16";
+    return false;
+  }
+  plan = HostPlan();
+  plan.T = T;
+  const size_t n = boards.size();
+  plan.K.assign(n, 0);
+  plan.Tshort.assign(n, 0);
+  plan.start.assign(n, 0);
+  plan.jshort.assign(n, 0);
+  int Kmax = 0;
+  for (size_t b = 0; b < n; ++b) {
+    const ChunkBoard& q = boards[b];
+    if (!q.tiles || q.generations < 0 || q.generations > ((int64_t)1 << 30)) {
+      err = "board " + std::to_string(b) + ": no tiles or generations out of range";
+      return false;
+    }
+    const int64_t K = (q.generations + T - 1) / T;
+    plan.K[b] = (int32_t)K;
+    plan.Tshort[b] = K > 0 ? (int32_t)(q.generations - (K - 1) * T) : 0;
+    plan.cell_updates += (double)q.rows * (double)q.cols * (double)q.generations;
+    Kmax = std::max<int>(Kmax, (int)K);
+    if (b == 0 || q.tiles->band_rows > plan.band_rows) plan.band_rows = q.tiles->band_rows;
+  }
+  // boards by pass count, most first (counting sort: K <= Kmax), then the
+  // early / late groups as in build_plan
+  std::vector<std::vector<int32_t>> byK((size_t)Kmax + 1);
+  for (size_t b = 0; b < n; ++b)
+    if (plan.K[b] > 0) byK[(size_t)plan.K[b]].push_back((int32_t)b);
+  // Boards that run every level (K == Kmax, most of a busy chunk) are split
+  // between the groups by load, so each group's stream carries about half
+  // of every level and the two streams fill each other's level tails (in a
+  // schedule of uneven K the early / late split does this by itself).
+  std::vector<double> load((size_t)Kmax, 0.0);
+  std::vector<int32_t> early, late;
+  double e_all = 0.0, l_all = 0.0;
+  for (int k = Kmax; k >= 1; --k) {
+    for (int32_t b : byK[(size_t)k]) {
+      const double w = (double)boards[b].rows * (double)(dwords_per_row(boards[b].cols) + 2);
+      double e = 0.0, l = 0.0;
+      if (k < Kmax) {
+        for (int L = 0; L < k; ++L) e += load[L];
+        for (int L = Kmax - k; L < Kmax; ++L) l += load[L];
+      } else {
+        e = e_all;
+        l = l_all;
+      }
+      if (l < e) {
+        l_all += w * k;
+        late.push_back(b);
+        plan.start[b] = Kmax - k;
+        plan.jshort[b] = k - 1;
+        for (int L = Kmax - k; L < Kmax; ++L) load[L] += w;
+      } else {
+        e_all += w * k;
+        early.push_back(b);
+        for (int L = 0; L < k; ++L) load[L] += w;
+      }
+    }
+  }
+  // waves: each board's own, its segments relabelled with the board's index;
+  // the groups' boards are already in descending K, so their waves are too
+  size_t nseg = 0, nwave = 0;
+  for (size_t b = 0; b < n; ++b)
+    if (plan.K[b] > 0) {
+      nseg += boards[b].tiles->segs.size();
+      nwave += boards[b].tiles->waves.size();
+    }
+  plan.segs.reserve(nseg);
+  plan.items.reserve(nwave);
+  std::vector<int32_t> maxk_e, maxk_l;
+  for (const std::vector<int32_t>* grp : {&early, &late}) {
+    if (grp == &late) plan.late_begin = (int32_t)plan.items.size();
+    for (int32_t b : *grp) {
+      const BoardTiles& t = *boards[b].tiles;
+      const int32_t base = (int32_t)plan.segs.size();
+      for (Segment sg : t.segs) {
+        sg.board = b;
+        plan.segs.push_back(sg);
+      }
+      for (const BoardTiles::Wave& w : t.waves) {
+        WaveItem it;
+        it.seg_begin = base + w.seg_begin;
+        it.nseg = w.nseg;
+        it.h = w.h;
+        it.maxK = plan.K[b];
+        it.flags = t.aligned ? kItemAligned : 0;
+        plan.items.push_back(it);
+        (grp == &late ? maxk_l : maxk_e).push_back(plan.K[b]);
+      }
+    }
+  }
+  plan.level_early.assign(Kmax, 0);
+  plan.level_late.assign(Kmax, 0);
+  plan.level_items.assign(Kmax, 0);
+  for (int32_t b : early)
+    if (plan.Tshort[b] < T) plan.early_masked = true;
+  for (int32_t b : late)
+    if (plan.Tshort[b] < T) plan.late_masked = true;
+  size_t ce = maxk_e.size(), cl = 0;
+  for (int L = 0; L < Kmax; ++L) {
+    while (ce > 0 && maxk_e[ce - 1] <= L) --ce;
+    while (cl < maxk_l.size() && maxk_l[cl] >= Kmax - L) ++cl;
+    plan.level_early[L] = (int32_t)ce;
+    plan.level_late[L] = (int32_t)cl;
+    plan.level_items[L] = (int32_t)(ce + cl);
+  }
+  for (size_t i = 0; i < plan.items.size(); ++i) {
+    const WaveItem& it = plan.items[i];
+    plan.lane_steps += (double)kWave * (it.h + 2 * T) * (double)it.maxK;
+  }
+  return true;
+}
+
+// Waves of a chunk's tiles at band height h (board_tiles' layout).
+static double chunk_waves(const std::vector<std::pair<int64_t, int64_t>>& boards, int h) {
+  double waves = 0.0;
+  for (const auto& rc : boards) {
+    const int64_t D = dwords_per_row(rc.second);
+    const int64_t ns = (D + kStripDwords - 1) / kStripDwords;
+    const int64_t nb = (rc.first + h - 1) / h;
+    const int64_t lanes = split(D, ns).size(0) + 2;
+    const int64_t per = std::max<int64_t>(1, kWave / lanes);
+    waves += (double)ns * (double)((nb + per - 1) / per);
+  }
+  return waves;
+}
+
+int chunk_band_rows(const std::vector<std::pair<int64_t, int64_t>>& boards, int T, int nsimd,
+                    int base) {
+  if (nsimd < 1) nsimd = 1024;
+  int h = std::max(base, 1);
+  const int floor_h = std::max(32, T);
+  while (h / 2 >= floor_h && chunk_waves(boards, h) < 2.0 * nsimd) h /= 2;
+  return h;
 }
 
 }  // namespace gol

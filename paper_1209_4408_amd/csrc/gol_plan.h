@@ -22,6 +22,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "gol_internal.h"
@@ -76,6 +77,43 @@ bool paired_ok(int64_t rows, int64_t cols, int T, const GridGeom& g, const char*
 // Builds the batch schedule.  Returns false with a message on invalid input.
 bool build_plan(const std::vector<BoardReq>& boards, int T, int band_rows, HostPlan& plan,
                 std::string& err);
+
+// Tiles of one board for schedules that keep a board's tiles between
+// launches (the server computes them once per board and band height): the
+// board's segments (board field 0, rows and dwords as in build_plan) and its
+// waves, each holding segments of this board only.  Strips narrow enough
+// that several fit a wave take consecutive bands of the same strip into one
+// wave (same board, same pass count: no lane ever idles for another board).
+struct BoardTiles {
+  struct Wave {
+    int32_t seg_begin;
+    int16_t nseg;
+    uint16_t h;  // tallest band of the wave
+  };
+  int band_rows = 0;
+  bool aligned = false;  // cols % 32 == 0
+  std::vector<Segment> segs;
+  std::vector<Wave> waves;
+};
+void board_tiles(int64_t rows, int64_t cols, int band_rows, BoardTiles& out);
+
+// One board of a chunk schedule: its tiles and the generations it advances.
+struct ChunkBoard {
+  const BoardTiles* tiles;
+  int64_t rows, cols, generations;
+};
+// The batch schedule of build_plan over boards that bring their own tiles
+// (no packing search: the cost is linear in the number of segments).
+bool build_chunk_plan(const std::vector<ChunkBoard>& boards, int T, HostPlan& plan,
+                      std::string& err);
+
+// Band height for a chunk over these boards (rows, cols) with T generations
+// per pass: `base` (the height timed fastest for a busy server) while its
+// tiles give every SIMD at least two waves; with fewer tiles, the height is
+// halved (not below 32 rows or T) until they do, so a lightly loaded server
+// still spreads its few boards over the chip.
+int chunk_band_rows(const std::vector<std::pair<int64_t, int64_t>>& boards, int T, int nsimd,
+                    int base);
 
 // Default band height for the single-board kernel: tall bands amortise the
 // 2T halo rows, but enough waves per SIMD are needed to hide latency, and the

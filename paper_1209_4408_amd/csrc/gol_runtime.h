@@ -24,6 +24,7 @@ void scratch_free(void* p, hipStream_t st);
 // receives the class); pinned_put_after returns the block to the pool once
 // the work queued on st so far has run.
 void* pinned_get(size_t bytes, size_t* cls);
+void pinned_put(void* pinned, size_t cls);  // at once: the caller knows it is idle
 int pinned_put_after(void* pinned, size_t cls, hipStream_t st);
 void reap_deferred(bool wait);
 
@@ -89,6 +90,14 @@ void fill_board_descs(DevicePlan& P);
 hipError_t enqueue_levels(const HostPlan& hp, const BoardDesc* boards, const Segment* segs,
                           const WaveItem* items, hipStream_t st, hipStream_t side,
                           hipEvent_t fork, hipEvent_t join);
+// Times the batch schedule of these boards (sizes and generation counts) on
+// zeroed scratch boards for every T in Ts and band height in bands; the
+// fastest pair goes to *T_out / *band_out (its seconds to *secs_out).
+int tune_batch(const std::vector<BoardReq>& boards, const std::vector<int>& Ts,
+               const std::vector<int>& bands, int* T_out, int* band_out, double* secs_out);
+// Band height of batched schedules when none is given or tuned.
+constexpr int kBatchBandRows = 96;
+
 // The normalising copies of a plan, then enqueue_levels.
 hipError_t enqueue_plan(const DevicePlan& P, hipStream_t st, hipStream_t side, hipEvent_t fork,
                         hipEvent_t join);

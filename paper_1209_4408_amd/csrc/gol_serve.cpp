@@ -3,30 +3,37 @@
 // One scheduler thread per server.  Each tick it
 //   1. admits queued requests, oldest first, while their two device buffers
 //      fit the HBM budget: device memory and the host-to-device copy are
-//      queued on the copy stream, and the compute stream will wait for it;
+//      queued on the upload stream, and the compute stream will wait for it;
 //   2. queues one chunk on the compute stream: every resident board advances
-//      min(chunk_generations, remaining) generations in one batched schedule
-//      of tile passes (boards admitted since the last tick join here);
+//      min(chunk length, remaining) generations in one batched schedule of
+//      tile passes (boards admitted since the last tick join here);
 //   3. for boards that finish in that chunk, queues the device-to-host copy
-//      (copy stream, after the chunk) and the release of their buffers.
+//      (download stream, after the chunk) and the release of their buffers.
 // Board state stays in device memory between chunks.  Up to two chunks are
 // in flight, so the host prepares the next while the device runs the last.
+// Each board keeps its tiles from chunk to chunk (rebuilt only when the band
+// height changes), so a chunk's schedule is assembled in time linear in its
+// tiles; its tables go through a ring of reused pinned and device buffers.
 //
 // The scheduler talks to the device through an executor.  HipExec is the
-// real one (two HIP streams, events, stream-ordered memory, pinned staging).
+// real one (compute streams, upload and download streams, events,
+// stream-ordered memory, the library's pinned staging pool).
 // HostExec keeps boards in host memory and completes every operation at once;
 // it exists so the scheduling policy (admission order, budget, chunking,
-// buffer bookkeeping, retirement, cancellation, failures) can be tested on a
-// machine without a GPU.  Its stand-in for a tile pass adds the number of
-// generations advanced to every word of the board, which composes like the
-// real step (two chunks of a and b generations equal one of a + b) and shows
-// whether the scheduler read and wrote the right buffers.
+// buffer bookkeeping, retirement, cancellation, failures) and each chunk's
+// schedule can be tested on a machine without a GPU.  It replays a chunk's
+// levels and tiles as the device would, standing in for a pass of t
+// generations over a tile by adding t to every 32-bit word of the tile,
+// which composes like the real step (two passes of a and b generations equal
+// a + b) and shows whether every pass read and wrote the right buffers and
+// covered every word once.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -58,8 +65,17 @@ class Exec {
  public:
   virtual ~Exec() = default;
   virtual int bind_thread() = 0;
+  virtual int simd_count() const { return 1024; }  // SIMDs of the device (band model)
+  // Host staging of results (pinned where the device is real): *cls
+  // identifies the block for host_free; cls 0 = plain malloc'd memory.
   virtual void* host_alloc(size_t bytes, size_t* cls) = 0;
   virtual void host_free(void* p, size_t cls) = 0;
+  // Host staging of a submitted board until its upload (plain memory: a
+  // burst of submissions pins nothing; the upload copies from it).
+  void* stage_alloc(size_t bytes, size_t* cls) {
+    *cls = 0;
+    return malloc(bytes ? bytes : 1);
+  }
   virtual int board_alloc(size_t bytes, void** p) = 0;  // in copy-queue order
   virtual void board_free_after_copies(void* p) = 0;
   virtual void board_free_after_chunks(void* p) = 0;
@@ -77,51 +93,28 @@ class Exec {
   virtual void sync() = 0;
 };
 
-// Pinned host blocks reused by size class (power of two), so steady-state
-// serving does not call hipHostMalloc.
-class PinnedPool {
- public:
-  ~PinnedPool() {
-    for (auto& kv : free_)
-      for (void* p : kv.second) (void)hipHostFree(p);
-  }
-  void* get(size_t bytes, size_t* cls_out) {
-    size_t cls = 4096;
-    while (cls < bytes) cls <<= 1;
-    *cls_out = cls;
-    {
-      std::lock_guard<std::mutex> lk(mu_);
-      auto& v = free_[cls];
-      if (!v.empty()) {
-        void* p = v.back();
-        v.pop_back();
-        return p;
-      }
-    }
-    void* p = nullptr;
-    if (hipHostMalloc(&p, cls, hipHostMallocDefault) != hipSuccess) return nullptr;
-    return p;
-  }
-  void put(void* p, size_t cls) {
-    if (!p) return;
-    std::lock_guard<std::mutex> lk(mu_);
-    free_[cls].push_back(p);
-  }
-
- private:
-  std::mutex mu_;
-  std::map<size_t, std::vector<void*>> free_;
-};
-
 class HipExec : public Exec {
  public:
   explicit HipExec(int device) : dev_(device) {}
   ~HipExec() override {
     sync();
-    reap();
+    reap();  // everything has run: every deferred release happens here
+    sync();
+    for (Slot& c : slots_) {
+      for (hipEvent_t ev : {c.start, c.end, c.fork, c.join})
+        if (ev) (void)hipEventDestroy(ev);
+      if (c.meta) (void)hipFree(c.meta);
+      if (c.pin) (void)hipHostFree(c.pin);
+    }
+    for (Copy* c : copies_free_) {
+      if (c->end) (void)hipEventDestroy(c->end);
+      delete c;
+    }
+    for (hipEvent_t ev : events_) (void)hipEventDestroy(ev);
     if (compute_) (void)hipStreamDestroy(compute_);
     if (compute2_) (void)hipStreamDestroy(compute2_);
-    if (copy_) (void)hipStreamDestroy(copy_);
+    if (up_) (void)hipStreamDestroy(up_);
+    if (down_) (void)hipStreamDestroy(down_);
   }
   int init() {
     int prev = 0;
@@ -129,7 +122,14 @@ class HipExec : public Exec {
     hipError_t e = hipSetDevice(dev_);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&compute_, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&compute2_, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&copy_, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&up_, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&down_, hipStreamNonBlocking);
+    for (Slot& c : slots_) {
+      if (e == hipSuccess) e = hipEventCreate(&c.start);
+      if (e == hipSuccess) e = hipEventCreate(&c.end);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c.fork, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&c.join, hipEventDisableTiming);
+    }
     if (e == hipSuccess) {
       hipMemPool_t pool;
       if (hipDeviceGetDefaultMemPool(&pool, dev_) == hipSuccess) {
@@ -137,17 +137,28 @@ class HipExec : public Exec {
         (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
       }
     }
+    int cus = 0;
+    if (e == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_) == hipSuccess &&
+        cus > 0)
+      nsimd_ = 4 * cus;
     (void)hipSetDevice(prev);
     return e == hipSuccess ? GOL_OK : hip_error(e, "server streams");
   }
+  int simd_count() const override { return nsimd_; }
   int bind_thread() override {
     hipError_t e = hipSetDevice(dev_);
     return e == hipSuccess ? GOL_OK : hip_error(e, "server: hipSetDevice");
   }
-  void* host_alloc(size_t bytes, size_t* cls) override { return pool_.get(bytes, cls); }
-  void host_free(void* p, size_t cls) override { pool_.put(p, cls); }
+  void* host_alloc(size_t bytes, size_t* cls) override { return pinned_get(bytes, cls); }
+  void host_free(void* p, size_t cls) override {
+    if (cls == 0)
+      free(p);
+    else
+      pinned_put(p, cls);
+  }
   int board_alloc(size_t bytes, void** p) override {
-    hipError_t e = hipMallocAsync(p, bytes, copy_);
+    hipError_t e = hipMallocAsync(p, bytes, up_);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       *p = nullptr;
@@ -155,114 +166,138 @@ class HipExec : public Exec {
     }
     return GOL_OK;
   }
-  void board_free_after_copies(void* p) override {
-    if (p) (void)hipFreeAsync(p, copy_);
-  }
-  void board_free_after_chunks(void* p) override {
-    if (p) (void)hipFreeAsync(p, compute_);
-  }
+  // A board's buffers go back to the stream-ordered pool on the stream that
+  // allocates them (the upload stream), and only once the host has seen
+  // their last use complete (the result download, or the chunks already
+  // queued for a cancelled board): a block released on one stream and
+  // handed by the pool to an allocation on another could be overwritten by
+  // the next admission's upload before the last use had run.
+  void board_free_after_copies(void* p) override { free_after(p, down_); }
+  void board_free_after_chunks(void* p) override { free_after(p, compute_); }
   int upload(void* dev, const void* host, size_t bytes) override {
-    hipError_t e = hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, copy_);
+    hipError_t e = hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, up_);
     return e == hipSuccess ? GOL_OK : hip_error(e, "server: host-to-device copy");
   }
   int chunks_wait_for_copies() override {
-    hipEvent_t ev;
-    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(ev, copy_);
+    hipEvent_t ev = nullptr;
+    hipError_t e = event_get(&ev);
+    if (e == hipSuccess) e = hipEventRecord(ev, up_);
     if (e == hipSuccess) e = hipStreamWaitEvent(compute_, ev, 0);
-    if (e != hipSuccess) return hip_error(e, "server: admission event");
-    pending_.push_back(Pending{ev, nullptr, 0});
+    if (e != hipSuccess) {
+      if (ev) events_.push_back(ev);
+      return hip_error(e, "server: admission event");
+    }
+    pending_.push_back(Pending{ev, nullptr, 0, nullptr});
     return GOL_OK;
   }
+  // A chunk's tables go through the next of a ring of slots, each keeping
+  // its pinned staging, its device table block and its four events from one
+  // chunk to the next (grown, never shrunk), so a chunk allocates nothing.
+  // At most two chunks are in flight, so the slot a chunk takes last served
+  // the chunk three before it, which has completed.
   int run_chunk(const std::vector<BoardDesc>& bd, const HostPlan& hp, Token* done) override {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t os = al(bd.size() * sizeof(BoardDesc));
     const size_t oi = os + al(hp.segs.size() * sizeof(Segment));
     const size_t mb = oi + al(hp.items.size() * sizeof(WaveItem));
-    size_t cls = 0;
-    char* pin = (char*)pool_.get(mb, &cls);
-    if (!pin) return set_error(GOL_EDEVICE, "server: pinned staging");
+    Slot& c = slots_[next_slot_];
+    next_slot_ = (next_slot_ + 1) % kSlots;
+    hipError_t e = hipSuccess;
+    if (c.busy) e = hipEventSynchronize(c.end);  // not reached while two chunks at most are queued
+    c.busy = false;
+    if (e == hipSuccess && c.pin_bytes < mb) {
+      if (c.pin) (void)hipHostFree(c.pin);
+      c.pin = nullptr;
+      c.pin_bytes = 0;
+      const size_t want = std::max(mb + mb / 2, (size_t)1 << 16);
+      e = hipHostMalloc(&c.pin, want, hipHostMallocDefault);
+      if (e == hipSuccess) c.pin_bytes = want;
+    }
+    if (e == hipSuccess && c.meta_bytes < mb) {
+      if (c.meta) (void)hipFreeAsync(c.meta, compute_);
+      c.meta = nullptr;
+      c.meta_bytes = 0;
+      const size_t want = std::max(mb + mb / 2, (size_t)1 << 16);
+      e = hipMallocAsync(&c.meta, want, compute_);
+      if (e == hipSuccess) c.meta_bytes = want;
+    }
+    if (e != hipSuccess) return hip_error(e, "server: chunk tables");
+    char* pin = (char*)c.pin;
     memcpy(pin, bd.data(), bd.size() * sizeof(BoardDesc));
     memcpy(pin + os, hp.segs.data(), hp.segs.size() * sizeof(Segment));
     memcpy(pin + oi, hp.items.data(), hp.items.size() * sizeof(WaveItem));
-    void* meta = nullptr;
-    hipError_t e = hipMallocAsync(&meta, mb, compute_);
-    if (e != hipSuccess) {
-      pool_.put(pin, cls);
-      return set_error(GOL_EDEVICE, "server: chunk tables: %s", hipGetErrorString(e));
-    }
-    Chunk* c = new Chunk();
-    e = hipEventCreate(&c->start);
-    if (e == hipSuccess) e = hipEventCreate(&c->end);
-    if (e == hipSuccess) e = hipEventRecord(c->start, compute_);
-    if (e == hipSuccess) e = hipMemcpyAsync(meta, pin, mb, hipMemcpyHostToDevice, compute_);
-    const BoardDesc* d_b = (const BoardDesc*)meta;
-    const Segment* d_s = (const Segment*)((char*)meta + os);
-    const WaveItem* d_i = (const WaveItem*)((char*)meta + oi);
-    hipEvent_t fork = nullptr, join = nullptr;
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
-    if (e == hipSuccess) e = enqueue_levels(hp, d_b, d_s, d_i, compute_, compute2_, fork, join);
-    if (fork) (void)hipEventDestroy(fork);  // the waits on them are queued
-    if (join) (void)hipEventDestroy(join);
-    (void)hipFreeAsync(meta, compute_);
-    if (e == hipSuccess) e = hipEventRecord(c->end, compute_);
-    if (e != hipSuccess) {
-      release(c);
-      return hip_error(e, "server: chunk launch");
-    }
-    const int rc = host_free_after(true, pin, cls);
-    if (rc) {
-      release(c);
-      return rc;
-    }
-    *done = c;
+    e = hipEventRecord(c.start, compute_);
+    if (e == hipSuccess) e = hipMemcpyAsync(c.meta, pin, mb, hipMemcpyHostToDevice, compute_);
+    const BoardDesc* d_b = (const BoardDesc*)c.meta;
+    const Segment* d_s = (const Segment*)((char*)c.meta + os);
+    const WaveItem* d_i = (const WaveItem*)((char*)c.meta + oi);
+    if (e == hipSuccess) e = enqueue_levels(hp, d_b, d_s, d_i, compute_, compute2_, c.fork, c.join);
+    if (e == hipSuccess) e = hipEventRecord(c.end, compute_);
+    if (e != hipSuccess) return hip_error(e, "server: chunk launch");
+    c.busy = true;
+    *done = &c;
     return GOL_OK;
   }
   int copies_wait_for(Token chunk) override {
-    hipError_t e = hipStreamWaitEvent(copy_, ((Chunk*)chunk)->end, 0);
+    hipError_t e = hipStreamWaitEvent(down_, ((Slot*)chunk)->end, 0);
     return e == hipSuccess ? GOL_OK : hip_error(e, "server: stream wait");
   }
   int download(void* host, const void* dev, size_t bytes, Token* done) override {
-    Chunk* c = new Chunk();
-    hipError_t e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, copy_);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->end, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(c->end, copy_);
+    Copy* c = nullptr;
+    if (!copies_free_.empty()) {
+      c = copies_free_.back();
+      copies_free_.pop_back();
+    } else {
+      c = new Copy();
+    }
+    hipError_t e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, down_);
+    if (e == hipSuccess && !c->end) e = event_get(&c->end);
+    if (e == hipSuccess) e = hipEventRecord(c->end, down_);
     if (e != hipSuccess) {
-      release(c);
+      copies_free_.push_back(c);
       return hip_error(e, "server: result copy");
     }
+    c->kind = 1;
     *done = c;
     return GOL_OK;
   }
   int host_free_after(bool compute, void* pinned, size_t cls) override {
-    hipEvent_t ev;
-    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventRecord(ev, compute ? compute_ : copy_);
-    if (e != hipSuccess) return hip_error(e, "server: event record");
-    pending_.push_back(Pending{ev, pinned, cls});
+    hipEvent_t ev = nullptr;
+    hipError_t e = event_get(&ev);
+    if (e == hipSuccess) e = hipEventRecord(ev, compute ? compute_ : up_);
+    if (e != hipSuccess) {
+      if (ev) events_.push_back(ev);
+      return hip_error(e, "server: event record");
+    }
+    pending_.push_back(Pending{ev, pinned, cls, nullptr});
     return GOL_OK;
   }
-  bool done(Token t) override { return hipEventQuery(((Chunk*)t)->end) == hipSuccess; }
+  bool done(Token t) override { return hipEventQuery(end_of(t)) == hipSuccess; }
   double seconds(Token t) override {
-    Chunk* c = (Chunk*)t;
+    const Tagged* g = (const Tagged*)t;
+    if (g->kind != 0) return 0.0;
+    const Slot* c = (const Slot*)t;
     float ms = 0.f;
-    if (!c->start || hipEventElapsedTime(&ms, c->start, c->end) != hipSuccess) return 0.0;
+    if (hipEventElapsedTime(&ms, c->start, c->end) != hipSuccess) return 0.0;
     return ms * 1e-3;
   }
   void release(Token t) override {
-    Chunk* c = (Chunk*)t;
-    if (!c) return;
-    if (c->start) (void)hipEventDestroy(c->start);
-    if (c->end) (void)hipEventDestroy(c->end);
-    delete c;
+    Tagged* g = (Tagged*)t;
+    if (!g) return;
+    if (g->kind == 0)
+      ((Slot*)t)->busy = false;
+    else
+      copies_free_.push_back((Copy*)t);
   }
   void reap() override {
     size_t k = 0;
     for (auto& p : pending_) {
       if (hipEventQuery(p.ev) == hipSuccess) {
-        (void)hipEventDestroy(p.ev);
-        pool_.put(p.pinned, p.cls);
+        events_.push_back(p.ev);
+        if (p.device)
+          (void)hipFreeAsync(p.device, up_);
+        else
+          host_free(p.pinned, p.cls);
       } else {
         pending_[k++] = p;
       }
@@ -271,23 +306,75 @@ class HipExec : public Exec {
   }
   void sync() override {
     if (compute_) (void)hipStreamSynchronize(compute_);
-    if (copy_) (void)hipStreamSynchronize(copy_);
+    if (compute2_) (void)hipStreamSynchronize(compute2_);
+    if (up_) (void)hipStreamSynchronize(up_);
+    if (down_) (void)hipStreamSynchronize(down_);
   }
 
  private:
-  struct Chunk {
-    hipEvent_t start = nullptr, end = nullptr;
+  // Tokens: a chunk's slot (kind 0) or a result copy (kind 1).
+  struct Tagged {
+    int kind = 0;
   };
+  struct Slot : Tagged {
+    hipEvent_t start = nullptr, end = nullptr, fork = nullptr, join = nullptr;
+    void* pin = nullptr;
+    size_t pin_bytes = 0;
+    void* meta = nullptr;
+    size_t meta_bytes = 0;
+    bool busy = false;
+  };
+  struct Copy : Tagged {
+    hipEvent_t end = nullptr;  // kept with the record for its next use
+  };
+  // Waits on the host for an event: then the pinned block returns to the
+  // pool, or the device block is freed on the upload stream.
   struct Pending {
     hipEvent_t ev;
     void* pinned;
     size_t cls;
+    void* device = nullptr;
   };
+  void free_after(void* p, hipStream_t st) {
+    if (!p) return;
+    hipEvent_t ev = nullptr;
+    if (event_get(&ev) == hipSuccess && hipEventRecord(ev, st) == hipSuccess) {
+      pending_.push_back(Pending{ev, nullptr, 0, p});
+      return;
+    }
+    (void)hipGetLastError();
+    // no event: wait for the stream, then free
+    if (ev) events_.push_back(ev);
+    (void)hipStreamSynchronize(st);
+    (void)hipFreeAsync(p, up_);
+  }
+  static constexpr int kSlots = 3;
+  hipEvent_t end_of(Token t) const {
+    const Tagged* g = (const Tagged*)t;
+    return g->kind == 0 ? ((const Slot*)t)->end : ((const Copy*)t)->end;
+  }
+  // Events without timing from a free list (created on first need).
+  hipError_t event_get(hipEvent_t* ev) {
+    if (!events_.empty()) {
+      *ev = events_.back();
+      events_.pop_back();
+      return hipSuccess;
+    }
+    return hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  }
   int dev_;
-  hipStream_t compute_ = nullptr, copy_ = nullptr;
+  int nsimd_ = 1024;
+  hipStream_t compute_ = nullptr;
+  // uploads (and the allocation of admitted boards) and result downloads (and
+  // the release of retired boards) on separate streams, so an admission never
+  // waits behind a download that waits for a chunk
+  hipStream_t up_ = nullptr, down_ = nullptr;
   hipStream_t compute2_ = nullptr;  // the late group of each chunk's schedule
-  PinnedPool pool_;
-  std::vector<Pending> pending_;  // touched by the scheduler thread under the server lock
+  Slot slots_[kSlots];
+  int next_slot_ = 0;
+  std::vector<Copy*> copies_free_;
+  std::vector<hipEvent_t> events_;  // free events
+  std::vector<Pending> pending_;    // touched by the scheduler thread under the server lock
 };
 
 // Boards in host memory, every operation complete on return (see the file
@@ -298,7 +385,7 @@ class HostExec : public Exec {
   explicit HostExec(int64_t fail_at) : fail_at_(fail_at) {}
   int bind_thread() override { return GOL_OK; }
   void* host_alloc(size_t bytes, size_t* cls) override {
-    *cls = bytes;
+    *cls = 0;
     return malloc(bytes ? bytes : 1);
   }
   void host_free(void* p, size_t) override { free(p); }
@@ -318,14 +405,42 @@ class HostExec : public Exec {
     return GOL_OK;
   }
   int chunks_wait_for_copies() override { return GOL_OK; }
+  // Replays the chunk's schedule as the device would run it: level by level,
+  // the early group's waves then the late group's, each segment taking the
+  // pass of its board that the level runs (the buffer it reads and writes,
+  // its generation count) exactly as the batch kernel selects them, and
+  // standing in for that pass by adding its generation count to every
+  // dword of the segment's tile.  A pass shorter than T in a level launched
+  // without the per-lane generation mask would run T generations on the
+  // device: reported as a device failure.
   int run_chunk(const std::vector<BoardDesc>& bd, const HostPlan& hp, Token* done) override {
     if (++chunks_ == fail_at_) return set_error(GOL_EDEVICE, "host executor: injected failure");
-    for (const BoardDesc& d : bd) {
-      const uint64_t g = (uint64_t)(d.K - 1) * (uint64_t)hp.T + (uint64_t)d.Tshort;
-      const uint64_t* src = (const uint64_t*)d.src0;
-      uint64_t* dst = (uint64_t*)d.w[(d.K - 1 + d.par) & 1];
-      const size_t words = (size_t)d.R * (size_t)(d.D / 2);
-      for (size_t i = 0; i < words; ++i) dst[i] = src[i] + g;
+    const int Kmax = (int)hp.level_items.size();
+    for (int L = 0; L < Kmax; ++L) {
+      for (int grp = 0; grp < 2; ++grp) {
+        const int begin = grp == 0 ? 0 : hp.late_begin;
+        const int count = grp == 0 ? hp.level_early[L] : hp.level_late[L];
+        const bool masked = grp == 0 ? (L == 0 && hp.early_masked)
+                                     : (L == Kmax - 1 && hp.late_masked);
+        for (int i = begin; i < begin + count; ++i) {
+          const WaveItem& w = hp.items[i];
+          for (int k = 0; k < w.nseg; ++k) {
+            const Segment& sg = hp.segs[w.seg_begin + k];
+            const BoardDesc& d = bd[sg.board];
+            const int j = L - d.start;
+            if (j < 0 || j >= d.K) continue;  // the board has no pass at this level
+            const uint32_t* src = j == 0 ? d.src0 : d.w[(j - 1 + d.par) & 1];
+            uint32_t* dst = d.w[(j + d.par) & 1];
+            const int t = j == d.jshort ? d.Tshort : hp.T;
+            if (t != hp.T && !masked)
+              return set_error(GOL_EDEVICE, "host executor: a %d-generation pass at level %d "
+                               "of a %d-generation schedule is not masked", t, L, hp.T);
+            for (int r = sg.r0; r < sg.r0 + (int)sg.h; ++r)
+              for (int p = sg.p0 + 1; p < sg.p0 + (int)sg.nlanes - 1; ++p)
+                dst[(size_t)r * d.D + p] = src[(size_t)r * d.D + p] + (uint32_t)t;
+          }
+        }
+      }
     }
     *done = &token_;
     return GOL_OK;
@@ -372,7 +487,7 @@ struct Request {
   uint64_t ticket = 0;
   int64_t rows = 0, cols = 0, W = 0, gens = 0;
   size_t bytes = 0;
-  void* pin_in = nullptr;
+  void* pin_in = nullptr;      // staged input (plain memory) until its upload
   size_t pin_in_cls = 0;
   void* pin_out = nullptr;
   size_t pin_out_cls = 0;
@@ -383,6 +498,7 @@ struct Request {
   bool cancel = false;
   bool retiring = false;       // final copy queued
   Token out_done = nullptr;    // device-to-host copy of the result done
+  BoardTiles tiles;            // the board's tiles at the band height last used
   double t_submit = 0, t_admit = 0, t_done = 0;
   std::string err;
 };
@@ -408,6 +524,10 @@ struct Server {
   uint64_t used_bytes = 0;
 
   std::deque<Token> chunks;                        // queued chunks, oldest first
+  std::deque<double> chunk_cu;                     // their cell updates
+  int T = 16;                                      // generations per pass (resolved)
+  int band = 96;                                   // band height of a busy chunk (resolved)
+  double rate = 0.0;  // cell updates per device second of completed chunks (running mean)
   gol_serve_stats stats{};
   std::thread th;
 
@@ -433,10 +553,38 @@ static void fail_all(Server& S, const std::string& msg) {
 static void reap(Server& S) {
   S.exec->reap();
   while (!S.chunks.empty() && S.exec->done(S.chunks.front())) {
-    S.stats.device_busy_s += S.exec->seconds(S.chunks.front());
+    const double secs = S.exec->seconds(S.chunks.front());
+    const double cu = S.chunk_cu.front();
+    S.stats.device_busy_s += secs;
+    if (secs > 0.0 && cu > 0.0)
+      S.rate = S.rate > 0.0 ? 0.75 * S.rate + 0.25 * (cu / secs) : cu / secs;
     S.exec->release(S.chunks.front());
     S.chunks.pop_front();
+    S.chunk_cu.pop_front();
   }
+}
+
+// Device time a chunk of an automatic length aims at: long enough that its
+// launches and host work are small beside it, short enough that a request
+// arriving meanwhile waits little before it joins.
+constexpr double kChunkTargetSeconds = 0.003;
+// Generations of the first chunks of an automatic length (no rate measured yet).
+constexpr int64_t kChunkFirstPasses = 15;
+constexpr int64_t kChunkMaxPasses = 256;
+
+// Generations every board advances in the next chunk (at most; fewer if it
+// finishes): the configured count, or (chunk_generations 0) as many whole
+// passes as the resident cells take about kChunkTargetSeconds of device time
+// at the rate measured on earlier chunks.
+static int64_t chunk_generations(const Server& S, const std::vector<Request*>& act) {
+  if (S.cfg.chunk_generations > 0) return S.cfg.chunk_generations;
+  if (S.rate <= 0.0) return kChunkFirstPasses * S.T;
+  double cells = 0.0;
+  for (const Request* r : act) cells += (double)r->rows * (double)r->cols;
+  const double g = kChunkTargetSeconds * S.rate / std::max(cells, 1.0);
+  const int64_t passes = std::min<int64_t>(kChunkMaxPasses,
+                                           std::max<int64_t>(1, (int64_t)std::ceil(g / S.T)));
+  return passes * S.T;
 }
 
 // Completed result copies -> Done.  Caller holds S.mu.
@@ -481,6 +629,9 @@ static int admit(Server& S, Request& r) {
 }
 
 // Build and queue one chunk over the resident boards.  Caller holds S.mu.
+// The band height is chosen per chunk for the boards in it (the occupancy
+// model of chunk_band_rows); each board keeps its tiles for that height, so
+// a chunk's schedule is assembled from them in time linear in the tiles.
 static int queue_chunk(Server& S, std::vector<uint64_t>& retire_now) {
   std::vector<Request*> act;
   for (uint64_t t : S.resident) {
@@ -489,16 +640,23 @@ static int queue_chunk(Server& S, std::vector<uint64_t>& retire_now) {
   }
   if (act.empty()) return GOL_OK;
   const auto t_plan0 = std::chrono::steady_clock::now();
-  const int T = S.cfg.t_block ? S.cfg.t_block : default_batch_T();
-  std::vector<BoardReq> req;
+  const int T = S.T;
+  const int64_t gchunk = chunk_generations(S, act);
+  std::vector<std::pair<int64_t, int64_t>> dims;
+  dims.reserve(act.size());
+  for (Request* r : act) dims.emplace_back(r->rows, r->cols);
+  const int h = chunk_band_rows(dims, T, S.exec->simd_count(), S.band);
+  std::vector<ChunkBoard> req;
   req.reserve(act.size());
   for (Request* r : act) {
-    const int64_t g = std::min<int64_t>(S.cfg.chunk_generations, r->gens - r->queued_gens);
-    req.push_back(BoardReq{r->rows, r->cols, g});
+    if (r->tiles.band_rows != h) board_tiles(r->rows, r->cols, h, r->tiles);
+    const int64_t g = std::min<int64_t>(gchunk, r->gens - r->queued_gens);
+    req.push_back(ChunkBoard{&r->tiles, r->rows, r->cols, g});
   }
   HostPlan hp;
   std::string err;
-  if (!build_plan(req, T, 64, hp, err)) return set_error(GOL_EINVAL, "server plan: %s", err.c_str());
+  if (!build_chunk_plan(req, T, hp, err))
+    return set_error(GOL_EINVAL, "server plan: %s", err.c_str());
   std::vector<BoardDesc> bd(act.size());
   for (size_t b = 0; b < act.size(); ++b) {
     Request& r = *act[b];
@@ -521,7 +679,10 @@ static int queue_chunk(Server& S, std::vector<uint64_t>& retire_now) {
   int rc = S.exec->run_chunk(bd, hp, &done);
   if (rc) return rc;
   S.chunks.push_back(done);
+  S.chunk_cu.push_back(hp.cell_updates);
   S.stats.chunks += 1;
+  S.stats.last_chunk_generations = gchunk;
+  S.stats.last_band_rows = h;
   S.stats.launches += (int64_t)hp.level_items.size();
   S.stats.cell_updates += hp.cell_updates;
   S.stats.max_resident = std::max<int64_t>(S.stats.max_resident, (int64_t)act.size());
@@ -676,8 +837,31 @@ static void scheduler(Server* Sp) {
   }
 }
 
+// The pass length and band height of every chunk, timed once at creation on
+// a resident set standing in for a busy server: square boards of 512 to
+// 8192 cells a side, four times as many of each size as of the next larger
+// (so every size holds the same cells: 1 of 8192^2 ... 256 of 512^2, 3.4e8
+// cells), advancing 48 generations (a multiple of every candidate), over
+// t_block 8, 12, 16 (or the given one) and band heights 64, 96, 128; the
+// fastest pair serves every chunk (a chunk with few tiles shortens the band,
+// see chunk_band_rows).
+static int tune_served(int device, int T_fixed, int* T_out, int* band_out) {
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_error(e, "server: hipSetDevice");
+  std::vector<BoardReq> set;
+  for (int k = 0; k < 5; ++k)
+    set.insert(set.end(), (size_t)1 << (2 * k), BoardReq{8192 >> k, 8192 >> k, 48});
+  const std::vector<int> Ts = T_fixed ? std::vector<int>{T_fixed} : std::vector<int>{8, 12, 16};
+  const int rc = tune_batch(set, Ts, {64, 96, 128}, T_out, band_out, nullptr);
+  (void)hipSetDevice(prev);
+  return rc;
+}
+
 static int check_config(const gol_serve_config* cfg) {
-  if (cfg->chunk_generations < 1) return set_error(GOL_EINVAL, "chunk_generations must be >= 1");
+  if (cfg->chunk_generations < 0)
+    return set_error(GOL_EINVAL, "chunk_generations must be >= 0 (0 = automatic)");
   if (cfg->hbm_budget_bytes == 0) return set_error(GOL_EINVAL, "hbm_budget_bytes must be > 0");
   if (cfg->t_block != 0 && !valid_T(cfg->t_block))
     return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8, 12 or 16");
@@ -693,7 +877,7 @@ struct gol_server {
 };
 
 static int start_server(const gol_serve_config* cfg, std::unique_ptr<Exec> exec,
-                        HostExec* host_exec, gol_server** out) {
+                        HostExec* host_exec, int tuned_T, int tuned_band, gol_server** out) {
   gol_server* s = nullptr;
   try {
     s = new gol_server();
@@ -702,6 +886,10 @@ static int start_server(const gol_serve_config* cfg, std::unique_ptr<Exec> exec,
   }
   Server& S = s->S;
   S.cfg = *cfg;
+  S.T = tuned_T > 0 ? tuned_T : (cfg->t_block ? cfg->t_block : default_batch_T());
+  S.band = tuned_band > 0 ? tuned_band : kBatchBandRows;
+  S.stats.t_block = S.T;
+  S.stats.busy_band_rows = S.band;
   S.t0 = std::chrono::steady_clock::now();
   S.exec = std::move(exec);
   S.host_exec = host_exec;
@@ -725,7 +913,10 @@ int gol_serve_create(const gol_serve_config* cfg, gol_server** out) {
     auto ex = std::make_unique<HipExec>(cfg->device);
     rc = ex->init();
     if (rc) return rc;
-    return start_server(cfg, std::move(ex), nullptr, out);
+    int T = cfg->t_block, band = 0;
+    rc = tune_served(cfg->device, cfg->t_block, &T, &band);
+    if (rc) return rc;
+    return start_server(cfg, std::move(ex), nullptr, T, band, out);
   } catch (const std::bad_alloc&) {
     return set_error(GOL_ENOMEM, "host allocation failed");
   }
@@ -740,7 +931,7 @@ int gol_debug_serve_create_host(const gol_serve_config* cfg, int64_t fail_at_chu
   try {
     auto ex = std::make_unique<HostExec>(fail_at_chunk);
     HostExec* raw = ex.get();
-    return start_server(cfg, std::move(ex), raw, out);
+    return start_server(cfg, std::move(ex), raw, 0, 0, out);
   } catch (const std::bad_alloc&) {
     return set_error(GOL_ENOMEM, "host allocation failed");
   }
@@ -769,8 +960,8 @@ int gol_serve_submit(gol_server* srv, const uint64_t* host_packed, int64_t rows,
     r->W = W;
     r->gens = generations;
     r->bytes = bytes;
-    r->pin_in = S.exec->host_alloc(bytes, &r->pin_in_cls);
-    if (!r->pin_in) return set_error(GOL_ENOMEM, "pinned staging for %zu bytes", bytes);
+    r->pin_in = S.exec->stage_alloc(bytes, &r->pin_in_cls);
+    if (!r->pin_in) return set_error(GOL_ENOMEM, "host staging for %zu bytes", bytes);
     memcpy(r->pin_in, host_packed, bytes);
     if (cols % 64) {
       // padding bits are not cells: the server keeps every board with them

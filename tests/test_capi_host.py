@@ -60,7 +60,7 @@ def test_packed_rejects_bad_arguments():
 def test_serve_create_rejects_bad_config():
     L = gol.lib()
     h = ctypes.c_void_p()
-    bad = [gol.ServeConfig(1 << 20, 0, 0, 0, 0), gol.ServeConfig(0, 8, 0, 0, 0),
+    bad = [gol.ServeConfig(1 << 20, -1, 0, 0, 0), gol.ServeConfig(0, 8, 0, 0, 0),
            gol.ServeConfig(1 << 20, 8, 0, 0, 3)]
     for cfg in bad:
         assert L.gol_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == gol.GOL_EINVAL
@@ -78,8 +78,9 @@ def test_set_allocator_pairs():
 # ---------------------------------------------------------------------------
 # Planner
 # ---------------------------------------------------------------------------
-def check_plan(rows, cols, gens, T, band):
-    segs, items, levels, late_begin, starts = gol.plan_tables(rows, cols, gens, T, band)
+def check_plan(rows, cols, gens, T, band, chunk=False):
+    out = gol.plan_tables(rows, cols, gens, T, band, chunk=chunk)
+    segs, items, levels, late_begin, starts = out[:5]
     n = len(rows)
     K = [(g + T - 1) // T for g in gens]
     Kmax = max(K) if K else 0
@@ -143,6 +144,58 @@ def test_plan_batched_mix_shape():
     # would hold only the few longest boards
     per_level = levels.sum(axis=1)
     assert per_level.min() > 0.5 * per_level.mean(), per_level
+
+
+@pytest.mark.parametrize("T", [1, 8, 16])
+@pytest.mark.parametrize("band", [0, 20, 96])
+def test_chunk_plan_covers_mixed_boards(T, band):
+    """A served chunk's schedule (each board tiled on its own) meets the
+    same invariants, and no wave mixes boards."""
+    rng = np.random.default_rng(11)
+    rows = [int(x) for x in rng.integers(1, 400, 40)] + [1, 2, 3, 8192]
+    cols = [int(x) for x in rng.integers(1, 3000, 40)] + [1, 2, 33, 8192]
+    gens = [int(x) for x in rng.integers(0, 60, 40)] + [5, 0, 7, 3]
+    segs, items, levels = check_plan(rows, cols, gens, T, band, chunk=True)
+    for it in items:
+        ss = segs[it["seg_begin"]: it["seg_begin"] + it["nseg"]]
+        assert len(set(int(b) for b in ss["board"])) == 1
+
+
+def test_chunk_plan_packs_bands_of_narrow_boards():
+    # a 600 x 100 board has 4-dword strips (6 lanes with halos): ten of its
+    # bands share each wave
+    segs, items, levels, lb, starts, band = gol.plan_tables([600], [100], [32], 16, 20,
+                                                           chunk=True)
+    assert band == 20
+    assert len(segs) == 30 and len(items) == 3
+    assert (items["nseg"] == 10).all()
+
+
+def test_chunk_band_model():
+    """Few resident boards get short bands (more waves to fill the SIMDs),
+    many get tall ones (less halo recompute)."""
+    one = gol.plan_tables([512], [512], [240], 16, 0, chunk=True)[5]
+    import seeded_inputs
+    specs = seeded_inputs.serve_specs(1209, n=2048, rate_per_s=1.0)
+    many = gol.plan_tables([s.rows for s in specs], [s.cols for s in specs],
+                           [min(s.generations, 240) for s in specs], 16, 0, chunk=True)[5]
+    assert one < many, (one, many)
+    assert one >= 16 and many <= 256
+
+
+def test_chunk_plan_time_is_linear():
+    """Assembling a chunk from per-board tiles costs time linear in the tiles:
+    4096 boards of the served mix take well under the build_plan search."""
+    import time
+    import seeded_inputs
+    specs = seeded_inputs.serve_specs(1209, n=4096, rate_per_s=1.0)
+    args = ([s.rows for s in specs], [s.cols for s in specs],
+            [min(s.generations, 240) for s in specs])
+    t0 = time.perf_counter()
+    segs = gol.plan_tables(*args, 16, 96, chunk=True)[0]
+    dt = time.perf_counter() - t0
+    assert len(segs) > 50000
+    assert dt < 1.0, dt
 
 
 def test_plan_rejects_bad_input():

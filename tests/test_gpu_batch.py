@@ -112,3 +112,50 @@ def test_mix_equals_alone():
     gol.batch_run(mix)
     for s, m, a in zip(specs, mix, alone):
         assert np.array_equal(from_dev(m.d_out), from_dev(a)), s
+
+
+def _tall_mixed(seed, n):
+    """Mixed boards, some tall enough to span several bands of every height."""
+    rng = np.random.default_rng(seed)
+    out = mixed_specs(seed, n)
+    for _ in range(6):
+        out.append((int(rng.integers(130, 420)), int(rng.integers(30, 2100)),
+                    int(rng.integers(1, 40))))
+    return out
+
+
+def _run_plan_and_check(specs, seed, **kw):
+    boards, want = [], []
+    for i, (R, C, G) in enumerate(specs):
+        b = rand_bytes(seed, i, R, C, 0.4)
+        boards.append(gol.BatchBoard(to_dev(oracle.pack(b)), gol.empty_packed(R, C), R, C, G))
+        want.append(expect_words(b, G))
+    p = gol.Plan(boards, **kw)
+    cfg = p.config()
+    p.run()
+    for i, bb in enumerate(boards):
+        got = from_dev(bb.d_out)
+        assert np.array_equal(got, want[i]), (kw, i, specs[i],
+                                              first_diff(got, want[i], specs[i][1]))
+    p.close()
+    return cfg
+
+
+@pytest.mark.parametrize("band", [48, 64, 96, 128])
+@pytest.mark.parametrize("T", [8, 12, 16])
+def test_plan_every_tuner_candidate_matches_oracle(T, band):
+    """Every (t_block, band_rows) the plan tuner can pick gives the oracle's boards."""
+    specs = _tall_mixed(31 + T + band, 36)
+    say("plan candidate", T, band)
+    cfg = _run_plan_and_check(specs, 12, t_block=T, band_rows=band)
+    assert cfg == {"t_block": T, "band_rows": band}
+
+
+def test_plan_tuned_choice_matches_oracle():
+    """With both fields 0 the plan times the candidates and keeps one of them."""
+    specs = _tall_mixed(77, 40)
+    cfg = _run_plan_and_check(specs, 13)
+    say("tuned plan", cfg)
+    assert cfg["t_block"] in (8, 12, 16) and cfg["band_rows"] in (48, 64, 96, 128)
+    cfg = _run_plan_and_check(specs, 14, t_block=4)  # band tuned only
+    assert cfg["t_block"] == 4 and cfg["band_rows"] in (48, 64, 96, 128)

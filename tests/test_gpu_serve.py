@@ -160,3 +160,41 @@ def test_serve_stream_poisson_small():
                 want = from_dev(gol.step_packed(to_dev(w), s.rows, s.cols, s.generations))
             say("request", s.board_id, s.rows, s.cols, s.generations)
             assert np.array_equal(out, want), s
+
+
+def _narrow_and_wide(seed):
+    """Requests whose tiles pack several bands of one board into a wave
+    (narrow boards) beside wide and tiny ones."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(30):
+        kind = i % 3
+        if kind == 0:
+            R, C = int(rng.integers(100, 900)), int(rng.integers(1, 200))   # narrow
+        elif kind == 1:
+            R, C = int(rng.integers(1, 120)), int(rng.integers(500, 3000))  # wide
+        else:
+            R, C = int(rng.integers(1, 40)), int(rng.integers(1, 40))       # tiny
+        G = int(rng.integers(0, 120))
+        out.append((rand_bytes(seed, i, R, C, float(rng.uniform(0.2, 0.6))), G))
+    return out
+
+
+@pytest.mark.parametrize("T", [0, 8, 12, 16])
+def test_serve_automatic_chunks_match_oracle(T):
+    """Chunks of the automatic length (and, T = 0, the pass length tuned at
+    creation) over narrow, wide and tiny boards give the oracle's results."""
+    reqs = _narrow_and_wide(40 + T)
+    with gol.Server(hbm_budget_bytes=1 << 30, chunk_generations=0, t_block=T) as srv:
+        tickets = [srv.submit(oracle.pack(b), *b.shape, G) for b, G in reqs]
+        for (b, G), t in zip(reqs, tickets):
+            R, C = b.shape
+            out = np.zeros((R, gol.words_per_row(C)), np.uint64)
+            srv.wait(t, out)
+            assert np.array_equal(out, expect_words(b, G)), (T, R, C, G)
+        st = srv.stats()
+    say("served T", T, "stats", st["t_block"], st["last_chunk_generations"],
+        st["last_band_rows"], st["chunks"])
+    assert st["t_block"] == (T or st["t_block"]) and st["t_block"] in (8, 12, 16)
+    assert st["last_chunk_generations"] % st["t_block"] == 0
+    assert st["last_band_rows"] >= 16

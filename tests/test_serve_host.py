@@ -1,9 +1,11 @@
 """CPU: the serving scheduler's policy, run over the host executor.
 
-The host executor keeps boards in host memory and stands in for a chunk of g
-generations by adding g (mod 2^64) to every word, so a request's result is
-its input plus its generation count only if every chunk read the buffer the
-previous chunk wrote and the result copy read the last one.  What these tests
+The host executor keeps boards in host memory and replays each chunk's
+schedule level by level and tile by tile as the device would, standing in for
+a pass of t generations by adding t to every 32-bit word of the tile, so a
+request's result is its input plus its generation count in every 32-bit word
+only if every pass read the buffer the previous pass wrote, every word was
+covered once per pass, and the result copy read the last one.  What these tests
 pin: results land in the right buffers across chunks, the HBM budget is never
 exceeded, admission is first-come first-served, chunks are as long as the
 configuration says, and cancellation, failures, polling and bad arguments
@@ -41,7 +43,8 @@ def board(seed, rows, cols, dirty=False):
 
 
 def expect(w, g):
-    return w + np.uint64(g)  # numpy wraps uint64 addition mod 2^64
+    """The stand-in's result: g added to every 32-bit word (numpy wraps)."""
+    return (w.view(np.uint32) + np.uint32(g & 0xFFFFFFFF)).view(np.uint64)
 
 
 def bytes_of(rows, cols):
@@ -106,6 +109,45 @@ def test_chunk_count_of_a_lone_request():
     assert st["chunks"] == -(-G // chunk)
     assert st["max_resident"] == 1
     assert st["launches"] >= st["chunks"]
+
+
+@pytest.mark.parametrize("T", [8, 16])
+def test_automatic_chunk_length_without_a_measured_rate(T):
+    """chunk_generations 0: until a chunk's device time is known (never, on
+    the host executor) each chunk runs 15 whole passes; results still land
+    in the right buffers, and the server reports the length and pass count."""
+    R, C, G = 9, 130, 1000
+    w = board(21, R, C)
+    with gol.Server(hbm_budget_bytes=1 << 20, chunk_generations=0, t_block=T,
+                    host_executor=True) as srv:
+        out = np.zeros_like(w)
+        srv.wait(srv.submit(w, R, C, G), out)
+        st = srv.stats()
+    assert np.array_equal(out, expect(w, G))
+    assert st["t_block"] == T
+    assert st["last_chunk_generations"] == 15 * T
+    assert st["chunks"] == -(-G // (15 * T))
+
+
+@pytest.mark.parametrize("T", [4, 8, 12, 16])
+@pytest.mark.parametrize("chunk", [0, 7, 16, 40])
+def test_mixed_requests_short_passes_and_groups(T, chunk):
+    """Chunks whose boards need different pass counts (short passes first in
+    the early group, last in the late one, masked levels) over boards narrow
+    enough to share waves: every 32-bit word advances by its request's
+    generation count."""
+    rng = np.random.default_rng(T * 100 + chunk)
+    reqs = []
+    for i in range(40):
+        R, C = int(rng.integers(1, 300)), int(rng.integers(1, 300))
+        reqs.append((board(1000 + i, R, C), R, C, int(rng.integers(0, 90))))
+    with gol.Server(hbm_budget_bytes=1 << 30, chunk_generations=chunk, t_block=T,
+                    host_executor=True) as srv:
+        tickets = [srv.submit(w, R, C, G) for w, R, C, G in reqs]
+        for (w, R, C, G), t in zip(reqs, tickets):
+            out = np.zeros_like(w)
+            srv.wait(t, out)
+            assert np.array_equal(out, expect(w, G)), (R, C, G)
 
 
 def test_budget_is_never_exceeded():
@@ -276,7 +318,7 @@ def test_device_failure_fails_unfinished_requests():
         assert e.value.code == GOL_EDEVICE
 
 
-@pytest.mark.parametrize("kw", [dict(chunk_generations=0), dict(hbm_budget_bytes=0),
+@pytest.mark.parametrize("kw", [dict(chunk_generations=-1), dict(hbm_budget_bytes=0),
                                 dict(t_block=3), dict(t_block=32)])
 def test_bad_configuration(kw):
     args = dict(hbm_budget_bytes=1 << 20, chunk_generations=4, host_executor=True)
