@@ -31,18 +31,43 @@ from . import ref  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gol_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of the oracle (the sanitizer builds below,
+# for CPU runs of the pins under ASan / UBSan or TSan); by default liboracle.so.
+_LIB = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
+# Sanitizer builds of build(sanitize=...): the compiler, its flags and the
+# runtime a process preloads.  ASan + UBSan with gcc; TSan with LLVM's clang
+# and OpenMP runtime, whose tool interface (libarcher, named by
+# OMP_TOOL_LIBRARIES) tells TSan about the parallel region's barriers.
+_LLVM = "/opt/rocm/llvm"
+SANITIZE = {"address": ("gcc", ["-fsanitize=address", "-fsanitize=undefined"]),
+            "thread": (_LLVM + "/bin/clang",
+                       ["-fsanitize=thread", f"-L{_LLVM}/lib", f"-Wl,-rpath,{_LLVM}/lib"])}
+SANITIZER_RUNTIME = {"address": ("gcc", "libasan.so"),
+                     "thread": (_LLVM + "/bin/clang", "libclang_rt.tsan-x86_64.so")}
+OMP_TOOL_LIBRARY = _LLVM + "/lib/libarcher.so"
 
 
-def build(force: bool = True) -> str:
-    """Compile the C oracle (plain -O2, OpenMP for the row-decomposed variant)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", _SRC,
+def build(force: bool = True, sanitize: str = "") -> str:
+    """Compile the C oracle (plain -O2, OpenMP for the row-decomposed variant);
+    sanitize ("address": ASan + UBSan, "thread": TSan) builds
+    liboracle_<kind>.so with those checks instead."""
+    out = _LIB if not sanitize else os.path.join(_HERE, f"liboracle_{sanitize}.so")
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        cc, extra = SANITIZE[sanitize] if sanitize else ("gcc", [])
+        if sanitize:
+            extra = extra + ["-g", "-fno-omit-frame-pointer"]
+        subprocess.check_call([cc, "-O2", "-fopenmp", *extra, "-shared", "-fPIC", _SRC,
                                "-o", tmp])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
+
+
+def sanitizer_runtime(kind: str) -> str:
+    cc, name = SANITIZER_RUNTIME[kind]
+    return subprocess.run([cc, f"-print-file-name={name}"], capture_output=True, text=True,
+                          check=True).stdout.strip()
 
 
 def _load():

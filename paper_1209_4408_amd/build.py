@@ -30,43 +30,93 @@ def _run(cmd: list[str]) -> None:
         raise RuntimeError("build step failed: " + " ".join(cmd))
 
 
+def _includes(path: str, seen: set) -> set:
+    """The source and the project headers it includes, recursively."""
+    import re
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    for line in open(path, encoding="utf-8", errors="replace"):
+        m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+        if m:
+            for d in (CSRC, INCLUDE):
+                cand = os.path.join(d, m.group(1))
+                if os.path.exists(cand):
+                    _includes(cand, seen)
+                    break
+    return seen
+
+
 def _stale(obj: str, src: str) -> bool:
-    """The object is missing or older than its source or any header."""
+    """The object is missing or older than its source or a header it includes."""
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
-    deps = [src] + [os.path.join(d, f) for d in (CSRC, INCLUDE) for f in os.listdir(d)
-                    if f.endswith(".h")]
-    return any(os.path.getmtime(d) > t for d in deps)
+    return any(os.path.getmtime(d) > t for d in _includes(src, set()))
+
+
+# Host-code sanitizer builds (CPU runs of the scheduler, planner and C ABI
+# checks): the host sources instrumented, the device code as always.  Each
+# -fsanitize= goes to the host compilation only.
+SANITIZERS = {"address": ["address", "undefined"], "thread": ["thread"]}
+
+
+def sanitized_lib(kind: str) -> str:
+    return os.path.join(OBJ + "_" + kind, "libgol.so")
+
+
+def sanitizer_runtime(kind: str) -> str:
+    """The clang runtime a process that loads a sanitized libgol preloads."""
+    name = {"address": "asan", "thread": "tsan"}[kind]
+    return subprocess.run([os.path.join(os.path.dirname(HIPCC), "..", "llvm", "bin", "clang"),
+                           f"-print-file-name=libclang_rt.{name}-x86_64.so"],
+                          capture_output=True, text=True, check=True).stdout.strip()
 
 
 def build(save_temps: bool = False, out: str = LIB, defines: tuple = (),
-          incremental: bool = False) -> str:
+          incremental: bool = False, sanitize: str = "") -> str:
     """Compile every source (or, incremental, those whose object is stale) and
-    link libgol.so."""
+    link libgol.so; sanitize ("address": ASan + UBSan, "thread": TSan)
+    instruments the host sources into _build_<kind>/libgol.so instead."""
     from concurrent.futures import ThreadPoolExecutor
-    os.makedirs(OBJ, exist_ok=True)
+    obj_dir = OBJ if not sanitize else OBJ + "_" + sanitize
+    if sanitize:
+        out = sanitized_lib(sanitize)
+    san = []
+    for k in SANITIZERS.get(sanitize, []):
+        san += ["-Xarch_host", f"-fsanitize={k}"]
+    if san:
+        san += ["-fno-omit-frame-pointer", "-g"]
+    os.makedirs(obj_dir, exist_ok=True)
     jobs, objs = [], []
     for s in DEVICE_SOURCES:
-        o = os.path.join(OBJ, s + ".o")
+        o = os.path.join(obj_dir, s + ".o")
         cmd = [HIPCC, *COMMON, *DEVICE, *[f"-D{d}" for d in defines], "-c",
                os.path.join(CSRC, s), "-o", o]
         if save_temps:
             cmd += ["-save-temps=obj"]
         jobs.append((cmd, o, os.path.join(CSRC, s)))
     for s in HOST_SOURCES:
-        o = os.path.join(OBJ, s + ".o")
-        jobs.append(([HIPCC, *COMMON, "-D__HIP_PLATFORM_AMD__", "-c", os.path.join(CSRC, s),
-                      "-o", o], o, os.path.join(CSRC, s)))
+        o = os.path.join(obj_dir, s + ".o")
+        jobs.append(([HIPCC, *COMMON, *san, "-D__HIP_PLATFORM_AMD__", "-c",
+                      os.path.join(CSRC, s), "-o", o], o, os.path.join(CSRC, s)))
     todo = [cmd for cmd, o, src in jobs if not incremental or defines or _stale(o, src)]
     with ThreadPoolExecutor(max_workers=min(8, max(1, len(todo)))) as ex:
         list(ex.map(_run, todo))
     objs = [o for _, o, _ in jobs]
     tmp = out + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"])
+    link = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
+    if san:
+        link += ["-shared-libsan", *[f for f in san if f.startswith("-fsanitize")]]
+    _run(link)
     os.replace(tmp, out)
     return out
 
 
 if __name__ == "__main__":
-    print(build(save_temps="--save-temps" in sys.argv, incremental="--incremental" in sys.argv))
+    kind = ""
+    for a in sys.argv[1:]:
+        if a.startswith("--sanitize="):
+            kind = a.split("=", 1)[1]
+    print(build(save_temps="--save-temps" in sys.argv, incremental="--incremental" in sys.argv,
+                sanitize=kind))
