@@ -331,6 +331,7 @@ def single_board(args, R, C, G, p, fixed_cfg="", compare_t1=False, cpu=True, cpu
         blk["t1"] = {"value": cells * G * n1 / wall1, "unit": "cell-updates/s", "steps": n1,
                      "timed_s": wall1,
                      "roofline": hbm_roofline(cells, dev1 / (n1 * G),
+                                              "k_step_t1" if C % 128 == 0 else
                                               f"k_board_pass<1, 3, {1 if C % 32 == 0 else 0}>")}
         blk["speedup_vs_t1"] = value / blk["t1"]["value"]
     del d_in, d_out

@@ -44,6 +44,8 @@ hipError_t launch_copy_clear_padding(const uint64_t* in, int64_t R, int64_t C, u
                                      hipStream_t st);
 // Device address of the current device's fixed scratch (kFixedScratchBytes).
 hipError_t fixed_scratch(void** out);
+hipError_t launch_step_t1(const uint32_t* src, uint32_t* dst, int32_t R, int32_t D, int band_rows,
+                          hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Errors
@@ -341,11 +343,22 @@ int resolve_config(int64_t R, int64_t C, const PassConfig& want, PassConfig* out
   return GOL_OK;
 }
 
+// Band height of the one-generation kernel: about eight waves per SIMD over
+// its 248-dword strips, bands of at least 16 rows.
+static int t1_band_rows(int64_t R, int64_t D, int nsimd) {
+  const int64_t strips = (D + 247) / 248;
+  const int64_t bands = std::max<int64_t>(1, 8 * (int64_t)nsimd / strips);
+  return (int)std::min<int64_t>(std::max<int64_t>(16, (R + bands - 1) / bands), 1 << 20);
+}
+
 hipError_t launch_pass(const PassConfig& c, const uint32_t* src, uint32_t* dst, int64_t R,
                        int64_t C, hipStream_t st) {
   const int32_t D = (int32_t)(2 * ((C + 63) / 64));
   if (c.layout == kLayoutResident)  // c.T generations in one launch
     return launch_board_lds(src, dst, (int32_t)R, (int32_t)C, D, c.T, st);
+  // one generation on rows of whole 128-bit words: the HBM-bound kernel
+  if (c.T == 1 && c.layout == kLayoutBand && !c.bounded && C % 128 == 0)
+    return launch_step_t1(src, dst, (int32_t)R, D, t1_band_rows(R, D, simd_count()), st);
   if (c.layout == kLayoutPaired)
     return launch_board_pass_half(c.T, src, dst, (int32_t)R, (int32_t)C, D,
                                   paired_geometry(R, C, c.band_rows, c.T, c.pd), c.pd, st);

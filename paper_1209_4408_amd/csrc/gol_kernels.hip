@@ -745,6 +745,140 @@ __global__ __launch_bounds__(64) void k_board_pass_half(PassArgs a, GridGeom g) 
 }
 
 // ---------------------------------------------------------------------------
+// One generation per launch on wide aligned boards (the HBM-bound form):
+// rows of D dwords with D % 4 == 0.  A wave owns a strip of 62 x 4 = 248
+// dwords plus one halo lane of four dwords on each side (lane l holds the
+// four consecutive dwords from 248 s - 4 + 4 l, modulo D, moved as one 128-bit
+// buffer access) and a band of rows; it sweeps rows r0 - 1 .. r0 + h (mod R)
+// keeping the horizontal 3-sums of the last two rows and emits row m - 1 when
+// row m arrives, so each row is read once per strip (plus the halo lanes and
+// the band's two halo rows) and written once.  Word-edge bits come from the
+// neighbouring dword: within the lane, or from the next lane by DPP; the halo
+// lanes' own results are wrong at their far edge and are not stored.  Rows
+// are requested kT1Prefetch steps ahead; lanes past the board load nothing
+// (their offsets fall outside the buffer and are dropped).
+// ---------------------------------------------------------------------------
+constexpr int kT1Lane = 4;                       // dwords per lane
+constexpr int kT1Useful = (kWave - 2) * kT1Lane;  // dwords a strip writes
+constexpr int kT1Prefetch = 8;                   // rows requested ahead
+
+struct T1Args {
+  const uint32_t* src;
+  uint32_t* dst;
+  int32_t R, D;
+  int32_t nstrips, nbands, band_q, band_r;  // balanced split of the rows into nbands
+};
+
+struct T1Row {
+  uint32_t x[kT1Lane];
+};
+
+__device__ __forceinline__ void t1_load(T1Row& r, const uint32_t* row, uint32_t bytes,
+                                        uint32_t qoff) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)uniform_ptr((uint32_t*)row), 0, (int)bytes,
+                                        kBufferDword3);
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, qoff, 0, 0);
+  r.x[0] = v[0];
+  r.x[1] = v[1];
+  r.x[2] = v[2];
+  r.x[3] = v[3];
+}
+
+__global__ __launch_bounds__(64) void k_step_t1(T1Args a) {
+  const int nitems = a.nstrips * a.nbands;
+  const int item = xcd_item(nitems);
+  if (item >= nitems) return;  // whole wave
+  const int s = item % a.nstrips, b = item / a.nstrips;
+  const int hb = a.band_q + (b < a.band_r ? 1 : 0);
+  const int rb = b * a.band_q + min(b, a.band_r);
+  const int lane = (int)threadIdx.x;
+  const int D = a.D, R = a.R;
+  // logical dword of the lane (the strip's west halo lane starts 4 dwords
+  // before it), and whether the lane is useful, the east halo or idle
+  const int p = s * kT1Useful - kT1Lane + lane * kT1Lane;
+  const int send = min(s * kT1Useful + kT1Useful, D);  // end of the strip's useful dwords
+  const bool useful = lane >= 1 && lane <= kWave - 2 && p < send;
+  const bool loads = lane == 0 || p < send + kT1Lane;  // useful or a halo lane
+  const uint32_t bytes = (uint32_t)D * 4u;
+  const uint32_t qoff = loads ? (uint32_t)(((p % D) + D) % D) * 4u : kDroppedOffset;
+  const uint32_t soff = useful ? (uint32_t)p * 4u : kDroppedOffset;
+  // rows rb - 1 .. rb + hb, modulo R
+  int rin = ((rb - 1) % R + R) % R;
+  const uint32_t* in_row = a.src + (int64_t)rin * D;
+  auto advance = [&]() {
+    ++rin;
+    in_row += D;
+    if (rin == R) {
+      rin = 0;
+      in_row = a.src;
+    }
+  };
+  int rout = rb;
+  uint32_t* out_row = a.dst + (int64_t)rb * D;
+  T1Row PF[kT1Prefetch];
+#pragma unroll
+  for (int k = 0; k < kT1Prefetch; ++k) {
+    t1_load(PF[k], in_row, bytes, qoff);
+    advance();
+  }
+  uint32_t lo[2][kT1Lane], hi[2][kT1Lane], xs[kT1Lane];
+  const int nsteps = hb + 2;
+  auto step = [&](int i, T1Row& r) {
+    uint32_t x[kT1Lane];
+#pragma unroll
+    for (int k = 0; k < kT1Lane; ++k) x[k] = r.x[k];
+    // request the row kT1Prefetch steps ahead into this slot
+    t1_load(r, in_row, bytes, qoff);
+    advance();
+    __builtin_amdgcn_sched_barrier(GOL_PREFETCH_FENCE_MASK);
+    const uint32_t west = from_prev_lane(x[kT1Lane - 1]);
+    const uint32_t east = from_next_lane(x[0]);
+    uint32_t l2[kT1Lane], h2[kT1Lane];
+#pragma unroll
+    for (int k = 0; k < kT1Lane; ++k) {
+      const uint32_t xw = k == 0 ? west : x[k - 1];
+      const uint32_t xe = k == kT1Lane - 1 ? east : x[k + 1];
+      const uint32_t xl = __builtin_amdgcn_alignbit(x[k], xw, 31);
+      const uint32_t xr = __builtin_amdgcn_alignbit(xe, x[k], 1);
+      l2[k] = xor3(xl, x[k], xr);
+      h2[k] = maj3(xl, x[k], xr);
+    }
+    if (i >= 2) {
+      uint32_t y[kT1Lane];
+#pragma unroll
+      for (int k = 0; k < kT1Lane; ++k)
+        y[k] = life_rule(lo[0][k], lo[1][k], l2[k], hi[0][k], hi[1][k], h2[k], xs[k]);
+      const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)uniform_ptr(out_row), 0, (int)bytes, kBufferDword3);
+      __builtin_amdgcn_raw_buffer_store_b128({y[0], y[1], y[2], y[3]}, rd, soff, 0, 0);
+      ++rout;
+      out_row += D;
+      if (rout == R) {
+        rout = 0;
+        out_row = a.dst;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kT1Lane; ++k) {
+      lo[0][k] = lo[1][k];
+      hi[0][k] = hi[1][k];
+      lo[1][k] = l2[k];
+      hi[1][k] = h2[k];
+      xs[k] = x[k];
+    }
+  };
+  int i = 0;
+  for (; i + kT1Prefetch <= nsteps; i += kT1Prefetch) {
+#pragma unroll
+    for (int k = 0; k < kT1Prefetch; ++k) step(i + k, PF[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kT1Prefetch; ++k)
+    if (i + k < nsteps) step(i + k, PF[k]);
+}
+
+// ---------------------------------------------------------------------------
 // Many boards: waves from a table, each made of one or more segments.
 // ---------------------------------------------------------------------------
 // A launch runs the waves items[0, nearly) and items[late_begin,
@@ -1016,6 +1150,26 @@ hipError_t launch_board_pass(int T, const uint32_t* src, uint32_t* dst, int32_t 
   GOL_LAUNCH_BAND(16, 12)
 #undef GOL_LAUNCH_BAND
   return hipErrorInvalidValue;
+}
+
+// One generation on a board with cols % 128 == 0 (D % 4 == 0): 248-dword
+// strips x bands of about band_rows rows.
+hipError_t launch_step_t1(const uint32_t* src, uint32_t* dst, int32_t R, int32_t D, int band_rows,
+                          hipStream_t st) {
+  T1Args a;
+  a.src = src;
+  a.dst = dst;
+  a.R = R;
+  a.D = D;
+  a.nstrips = (D + kT1Useful - 1) / kT1Useful;
+  const int64_t nb = ((int64_t)R + band_rows - 1) / band_rows;
+  a.nbands = (int32_t)(nb < 1 ? 1 : nb);
+  a.band_q = R / a.nbands;
+  a.band_r = R % a.nbands;
+  const int64_t nitems = (int64_t)a.nstrips * a.nbands;
+  const int64_t grid = ((nitems + 7) / 8) * 8;
+  hipLaunchKernelGGL(k_step_t1, dim3((unsigned)grid), dim3(64), 0, st, a);
+  return hipGetLastError();
 }
 
 // Whole board resident in LDS for G generations; resident_fits(R, C) must

@@ -49,6 +49,19 @@ def test_odd_widths(C):
         check(b, 11, T)
 
 
+@pytest.mark.parametrize("R,C", [(1, 128), (2, 256), (3, 384), (5, 128), (37, 640), (300, 8192),
+                                 (129, 16384 + 128), (64, 8064), (1000, 33 * 128)])
+def test_one_generation_kernel_on_128_aligned_rows(R, C):
+    """Rows of whole 128-bit words take the one-generation kernel (256-dword
+    strips, four dwords per lane): single passes, a pass count in place, and
+    every remainder pass of 1 generation, against the oracle."""
+    b = rand_bytes(2024, R + C, R, C, 0.45)
+    for G in (1, 2, 5):
+        check(b, G, 1)
+    check(b, 3, 1, inplace=True)
+    check(b, 17, 8)  # 2 passes of 8 and one of 1
+
+
 @pytest.mark.parametrize("R,C", [(1, 200), (2, 77), (3, 4097), (257, 4095), (200, 8191), (70, 3969),
                                  (64, 3968), (33, 2047)])
 def test_shapes_spanning_several_tiles(R, C):
