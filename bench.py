@@ -382,6 +382,23 @@ def batched(args, cpu=True):
     with torch.cuda.stream(st):
         wall, dev = timed_region(torch, lambda: plan.run(st), args.steps, args.warmup, st)
     plan.close()
+    graph_out = d_out.clone()
+    # the persistent work-queue form of the same schedule (same t_block and
+    # band height): one launch, per-board pass counters
+    log("timing the persistent work-queue form")
+    qplan = gol.Plan(boards, t_block=T, band_rows=pcfg["band_rows"], queue=True)
+    d_out.zero_()
+    with torch.cuda.stream(st):
+        wall_q, dev_q = timed_region(torch, lambda: qplan.run(st), args.steps, args.warmup, st)
+    gave_up = qplan.queue_gave_up()
+    qplan.close()
+    queue_blk = {"value": work * args.steps / wall_q, "unit": "cell-updates/s",
+                 "steps": args.steps, "timed_s": wall_q, "device_s": dev_q,
+                 "gave_up": gave_up, "equals_graph": bool(torch.equal(d_out, graph_out)),
+                 "what": "one persistent launch (resident waves take per-board pass items "
+                         "from a queue, device-scope counters between passes), same t_block "
+                         "and band height"}
+    del graph_out
     value = work * args.steps / wall
     per = dev / args.steps
     roof = alu_roofline(work, per, f"k_batch_pass<{T}, *>", launches=info["levels"],
@@ -396,7 +413,7 @@ def batched(args, cpu=True):
                                   "schedule", "boards": len(specs), "seed": SEED,
                       "t_block": T, "band_rows": pcfg["band_rows"],
                       "tuned": not args.t_block, "cell_updates": work},
-           "roofline": roof, "plan": info}
+           "roofline": roof, "plan": info, "queue_form": queue_blk}
     if not args.no_plain:
         log("plain per-board loop (library default configuration)")
         plain_steps = 1

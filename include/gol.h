@@ -131,6 +131,8 @@ int gol_step_packed_noalloc(const uint64_t* d_in, int64_t rows, int64_t cols,
 #define GOL_LAYOUT_BAND 1
 #define GOL_LAYOUT_PAIRED 2
 #define GOL_LAYOUT_RESIDENT 3
+/* Batch plans only (gol_plan_create_cfg): the persistent work-queue form. */
+#define GOL_LAYOUT_QUEUE 4
 typedef struct gol_pass_config {
   int32_t t_block;
   int32_t band_rows;
@@ -265,6 +267,15 @@ int gol_plan_create(const gol_board* boards, int64_t n, int t_block, gol_plan** 
  * (of every k-th board when they would take more than 1 GiB; the defaults,
  * 16 and 96, when the device has no room), and keeps the fastest.  Creation
  * is synchronous; the buffers of `boards` are not touched.
+ * config->layout GOL_LAYOUT_QUEUE selects the persistent work-queue form
+ * instead of the level-by-level schedule: one launch of as many waves as the
+ * device holds at once, taking items (one wave of one board's tiles in one
+ * pass) from a queue in pass order, each waiting until its board's previous
+ * pass is complete (device-scope counters, release / acquire fences, waits
+ * bounded: a wait that gives up stops the launch early, which
+ * gol_debug_plan_queue_gave_up reports).  t_block 8, 12 or 16 (0: 12),
+ * band_rows 0: 96; nothing is tuned.  It exists to measure the two forms
+ * against each other; the level schedule is the default.
  */
 int gol_plan_create_cfg(const gol_board* boards, int64_t n, const gol_pass_config* config,
                         gol_plan** out);

@@ -56,6 +56,15 @@ int gol_debug_chunk_plan_tables(const int64_t* rows, const int64_t* cols, const 
                                 int64_t* nlevels, int32_t* band_used);
 
 /*
+ * For a plan of the queue form (GOL_LAYOUT_QUEUE): waits for its queued runs
+ * and sets *gave_up to 1 if a wave of the last run gave up waiting for a
+ * board's previous pass (its results are then not to be used), else 0; 0 for
+ * other plans.
+ */
+typedef struct gol_plan gol_plan;
+int gol_debug_plan_queue_gave_up(gol_plan* plan, int32_t* gave_up);
+
+/*
  * A server whose "device" is host memory, for testing the serving scheduler
  * (admission by budget, chunking, the buffer that holds each board's state,
  * retirement, cancellation, failure handling) without a GPU.  Every queued

@@ -109,6 +109,7 @@ def lib():
             "gol_plan_create_cfg": (c_int, [vp, i64, ctypes.POINTER(PassConfig),
                                             ctypes.POINTER(vp)]),
             "gol_plan_config": (c_int, [vp, ctypes.POINTER(PassConfig)]),
+            "gol_debug_plan_queue_gave_up": (c_int, [vp, ctypes.POINTER(ctypes.c_int32)]),
             "gol_plan_run": (c_int, [vp, vp]),
             "gol_plan_info": (c_int, [vp, ctypes.POINTER(i64), ctypes.POINTER(i64),
                                       ctypes.POINTER(ctypes.c_double)]),
@@ -232,6 +233,7 @@ def empty_packed(rows: int, cols: int, device="cuda"):
 LAYOUT_BAND = 1
 LAYOUT_PAIRED = 2
 LAYOUT_RESIDENT = 3  # whole board in one workgroup's LDS for a run (small boards)
+LAYOUT_QUEUE = 4  # batch plans: the persistent work-queue form
 
 
 def step_packed(d_in, rows: int, cols: int, generations: int, d_out=None, stream=None,
@@ -413,12 +415,15 @@ def batch_run(boards: Sequence[BatchBoard], stream=None) -> None:
 class Plan:
     """A batch schedule built once and replayed (HIP graph) on the same buffers."""
 
-    def __init__(self, boards: Sequence[BatchBoard], t_block: int = 0, band_rows: int = 0):
-        """t_block / band_rows 0: tuned at creation (gol_plan_create_cfg)."""
+    def __init__(self, boards: Sequence[BatchBoard], t_block: int = 0, band_rows: int = 0,
+                 queue: bool = False):
+        """t_block / band_rows 0: tuned at creation (gol_plan_create_cfg);
+        queue=True: the persistent work-queue form (GOL_LAYOUT_QUEUE)."""
         self._boards = list(boards)  # keep the tensors alive
         arr = _board_array(self._boards)
         h = ctypes.c_void_p()
-        c = PassConfig(t_block=int(t_block), band_rows=int(band_rows))
+        c = PassConfig(t_block=int(t_block), band_rows=int(band_rows),
+                       layout=LAYOUT_QUEUE if queue else 0)
         _check(lib().gol_plan_create_cfg(ctypes.cast(arr, ctypes.c_void_p), len(self._boards),
                                          ctypes.byref(c), ctypes.byref(h)))
         self._h = h
@@ -427,7 +432,15 @@ class Plan:
         """The plan's generations per pass and band height (tuned or given)."""
         c = PassConfig()
         _check(lib().gol_plan_config(self._h, ctypes.byref(c)))
-        return {"t_block": c.t_block, "band_rows": c.band_rows}
+        return {"t_block": c.t_block, "band_rows": c.band_rows,
+                **({"layout": "queue"} if c.layout == LAYOUT_QUEUE else {})}
+
+    def queue_gave_up(self) -> bool:
+        """Queue form: whether a wave of the last run gave up waiting (waits
+        for the plan's runs)."""
+        v = ctypes.c_int32()
+        _check(lib().gol_debug_plan_queue_gave_up(self._h, ctypes.byref(v)))
+        return bool(v.value)
 
     def run(self, stream=None) -> None:
         _check(lib().gol_plan_run(self._h, _stream_handle(stream)))

@@ -46,6 +46,10 @@ hipError_t launch_copy_clear_padding(const uint64_t* in, int64_t R, int64_t C, u
 hipError_t fixed_scratch(void** out);
 hipError_t launch_step_t1(const uint32_t* src, uint32_t* dst, int32_t R, int32_t D, int band_rows,
                           hipStream_t st);
+hipError_t launch_batch_queue(int T, const BoardDesc* boards, const Segment* segs,
+                              const QueueItem* items, const int32_t* per_pass, int nitems,
+                              uint32_t* ctl, int nboards, int waves, hipStream_t st);
+int batch_queue_waves(int T);
 
 // ---------------------------------------------------------------------------
 // Errors
@@ -939,6 +943,13 @@ using namespace gol;
 struct gol_plan {
   DevicePlan P;
   void* meta = nullptr;
+  // the persistent work-queue form (GOL_LAYOUT_QUEUE): its own tables
+  bool queue = false;
+  QueuePlan Q;
+  const QueueItem* d_qitems = nullptr;
+  const int32_t* d_per_pass = nullptr;
+  uint32_t* d_ctl = nullptr;
+  int qwaves = 0;
   int device = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -965,6 +976,57 @@ static hipError_t plan_mark_run(gol_plan* p, hipStream_t st) {
   if (e == hipSuccess) p->runs.push_back(ev);
   else if (ev) (void)hipEventDestroy(ev);
   return e;
+}
+
+// Tables of the queue form: board descriptors (short pass first), segments,
+// items, items per pass, control words.
+static int setup_queue(gol_plan* p, int T, int band) {
+  std::vector<BoardReq> req;
+  for (const gol_board& g : p->P.boards) req.push_back(BoardReq{g.rows, g.cols, g.generations});
+  std::string err;
+  if (!build_queue_plan(req, T, band, p->Q, err)) return set_error(GOL_EINVAL, "%s", err.c_str());
+  for (BoardDesc& d : p->P.h_boards) d.jshort = 0;  // pass j reads / writes as before
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t n = p->P.h_boards.size();
+  const size_t ob = 0, os = al(n * sizeof(BoardDesc));
+  const size_t oi = os + al(p->Q.segs.size() * sizeof(Segment));
+  const size_t op = oi + al(p->Q.items.size() * sizeof(QueueItem));
+  const size_t oc = op + al(n * sizeof(int32_t));
+  const size_t mb = oc + al((kQueueCtlHeader + n) * sizeof(uint32_t));
+  hipError_t e = hipMalloc(&p->meta, mb);
+  if (e != hipSuccess) return set_error(GOL_ENOMEM, "hipMalloc queue tables: %s", hipGetErrorString(e));
+  std::vector<char> host(mb, 0);
+  memcpy(host.data() + ob, p->P.h_boards.data(), n * sizeof(BoardDesc));
+  memcpy(host.data() + os, p->Q.segs.data(), p->Q.segs.size() * sizeof(Segment));
+  memcpy(host.data() + oi, p->Q.items.data(), p->Q.items.size() * sizeof(QueueItem));
+  memcpy(host.data() + op, p->Q.per_pass.data(), n * sizeof(int32_t));
+  e = hipMemcpy(p->meta, host.data(), mb, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_error(e, "hipMemcpy queue tables");
+  p->P.d_boards = (BoardDesc*)((char*)p->meta + ob);
+  p->P.d_segs = (Segment*)((char*)p->meta + os);
+  p->d_qitems = (const QueueItem*)((char*)p->meta + oi);
+  p->d_per_pass = (const int32_t*)((char*)p->meta + op);
+  p->d_ctl = (uint32_t*)((char*)p->meta + oc);
+  p->qwaves = batch_queue_waves(T);
+  if (p->qwaves <= 0) p->qwaves = 4 * simd_count();
+  return GOL_OK;
+}
+
+static hipError_t enqueue_queue(const gol_plan* p, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int b : p->P.zero_gen) {
+    const gol_board& g = p->P.boards[b];
+    e = launch_copy_clear_padding(g.d_in, g.rows, g.cols, g.d_out, st);
+    if (e != hipSuccess) return e;
+  }
+  for (int b : p->P.copy_first) {
+    const gol_board& g = p->P.boards[b];
+    e = launch_copy_clear_padding(g.d_in, g.rows, g.cols, p->P.d_scratch + p->P.scratch_off[b], st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_batch_queue(p->Q.T, p->P.d_boards, p->P.d_segs, p->d_qitems, p->d_per_pass,
+                            (int)p->Q.items.size(), p->d_ctl, (int)p->P.h_boards.size(),
+                            p->qwaves, st);
 }
 
 extern "C" {
@@ -1183,19 +1245,26 @@ int gol_plan_create_cfg(const gol_board* boards, int64_t n, const gol_pass_confi
     gol_pass_config cfg{};
     if (config) cfg = *config;
     if (cfg.t_block < 0 || cfg.band_rows < 0 || cfg.band_rows > 65535 || cfg.prefetch != 0 ||
-        cfg.layout != 0)
+        (cfg.layout != 0 && cfg.layout != GOL_LAYOUT_QUEUE))
       return set_error(GOL_EINVAL,
                        "a batch plan takes t_block (0, 1, 2, 4, 8, 12, 16) and band_rows "
-                       "(0 .. 65535); prefetch and layout must be 0");
+                       "(0 .. 65535); prefetch must be 0 and layout 0 or GOL_LAYOUT_QUEUE");
     if (cfg.t_block != 0 && !valid_T(cfg.t_block))
       return set_error(GOL_EINVAL, "t_block must be 0, 1, 2, 4, 8, 12 or 16 (got %d)",
                        cfg.t_block);
+    const bool queue = cfg.layout == GOL_LAYOUT_QUEUE;
     int T = cfg.t_block, band = cfg.band_rows;
-    if (T == 0 || band == 0) {
+    if (queue) {
+      if (!T) T = 12;
+      if (!band) band = kBatchBandRows;
+      if (!(T == 8 || T == 12 || T == 16))
+        return set_error(GOL_EINVAL, "the queue form runs t_block 8, 12 or 16 (got %d)", T);
+    } else if (T == 0 || band == 0) {
       int rc = tune_plan(boards, n, &T, &band);
       if (rc) return rc;
     }
     p = new gol_plan();
+    p->queue = queue;
     int rc = plan_boards(boards, n, T, band, p->P);
     if (rc) {
       delete p;
@@ -1215,6 +1284,16 @@ int gol_plan_create_cfg(const gol_board* boards, int64_t n, const gol_pass_confi
       }
     }
     fill_board_descs(p->P);
+    if (queue) {
+      rc = setup_queue(p, T, band);
+      if (rc) {
+        (void)hipFree(p->P.d_scratch);
+        delete p;
+        return rc;
+      }
+      *out = p;
+      return GOL_OK;
+    }
     size_t ob, os, oi;
     const size_t mb = meta_bytes(p->P, &ob, &os, &oi);
     e = hipMalloc(&p->meta, mb);
@@ -1255,14 +1334,16 @@ int gol_plan_run(gol_plan* p, void* stream) {
   if (!p) return set_error(GOL_EINVAL, "null plan");
   hipStream_t st = (hipStream_t)stream;
   if (st == nullptr) {
-    hipError_t e = enqueue_plan(p->P, st, p->side, p->fork, p->join);
+    hipError_t e = p->queue ? enqueue_queue(p, st) : enqueue_plan(p->P, st, p->side, p->fork,
+                                                                    p->join);
     if (e == hipSuccess) e = plan_mark_run(p, st);
     return e == hipSuccess ? GOL_OK : hip_error(e, "gol_plan_run");
   }
   if (!p->exec) {
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
-    hipError_t el = enqueue_plan(p->P, st, p->side, p->fork, p->join);
+    hipError_t el = p->queue ? enqueue_queue(p, st)
+                             : enqueue_plan(p->P, st, p->side, p->fork, p->join);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(st, &g);
     if (el != hipSuccess) {
@@ -1288,6 +1369,7 @@ int gol_plan_config(const gol_plan* p, gol_pass_config* out) {
   *out = gol_pass_config{};
   out->t_block = p->P.hp.T;
   out->band_rows = p->P.hp.band_rows;
+  out->layout = p->queue ? GOL_LAYOUT_QUEUE : 0;
   return GOL_OK;
 }
 
@@ -1376,6 +1458,24 @@ int gol_debug_plan_tables(const int64_t* rows, const int64_t* cols, const int64_
   } catch (const std::bad_alloc&) {
     return set_error(GOL_ENOMEM, "host allocation failed");
   }
+}
+
+int gol_debug_plan_queue_gave_up(gol_plan* p, int32_t* gave_up) {
+  if (!p || !gave_up) return set_error(GOL_EINVAL, "null argument");
+  *gave_up = 0;
+  if (!p->queue) return GOL_OK;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    for (hipEvent_t ev : p->runs) {
+      const hipError_t e = hipEventSynchronize(ev);
+      if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
+    }
+  }
+  uint32_t w = 0;
+  const hipError_t e = hipMemcpy(&w, p->d_ctl + 1, sizeof(w), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_error(e, "hipMemcpy queue status");
+  *gave_up = (int32_t)w;
+  return GOL_OK;
 }
 
 int gol_debug_chunk_plan_tables(const int64_t* rows, const int64_t* cols, const int64_t* gens,

@@ -111,6 +111,23 @@ struct WaveItem {
 };
 constexpr int32_t kItemAligned = 1;
 
+// Persistent work-queue form of a batch schedule: one launch whose waves take
+// items in queue order (an atomic counter), each item one wave of one
+// board's tiles in one pass.  Pass j of a board waits until the board's
+// counter of finished items reaches j x (its items per pass); items are
+// queued pass by pass, so an item waits only on items taken before it.
+struct QueueItem {
+  int32_t seg_begin;
+  int16_t nseg;
+  uint16_t h;      // tallest band of the item's segments
+  int32_t board;
+  int32_t pass;
+  int32_t flags;   // kItemAligned
+};
+// Control words of a queue launch (zeroed before it): next item, error
+// (a wait gave up), then one finished-item counter per board.
+constexpr int kQueueCtlHeader = 2;
+
 // Geometry of a single large board split into strips x bands, one wave per
 // tile, computed from the block index (no tables).
 struct GridGeom {

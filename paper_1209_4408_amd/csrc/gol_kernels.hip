@@ -923,6 +923,86 @@ __global__ __launch_bounds__(64) void k_batch_pass(const BoardDesc* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Many boards in one persistent launch: each wave takes items from a queue
+// (QueueItem, in pass order) until it is empty.  Before an item of pass j it
+// waits for the board's counter to reach j x (items per pass): every tile of
+// pass j - 1 has stored (the rows this pass reads) and has finished reading
+// the buffer this pass overwrites.  Publication goes through device-scope
+// release / acquire fences around the counter; a wait gives up after a
+// bounded number of sleeps (setting the error word, which every wave checks,
+// so the launch always drains).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kQueueSpinLimit = 1u << 22;  // sleeps of ~128 clocks each before giving up
+
+template <int TM>
+__global__ __launch_bounds__(64) void k_batch_queue(const BoardDesc* __restrict__ boards,
+                                                    const Segment* __restrict__ segs,
+                                                    const QueueItem* __restrict__ items,
+                                                    const int32_t* __restrict__ per_pass,
+                                                    int nitems, uint32_t* ctl) {
+  const int lane = (int)threadIdx.x;
+  uint32_t* const next = ctl;
+  uint32_t* const error = ctl + 1;
+  uint32_t* const done = ctl + kQueueCtlHeader;
+  while (true) {
+    uint32_t it = 0;
+    if (lane == 0) it = __hip_atomic_fetch_add(next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    it = (uint32_t)__builtin_amdgcn_readfirstlane((int)it);
+    if ((int)it >= nitems) return;
+    if (__hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return;
+    const QueueItem q = items[it];
+    const uint32_t need = (uint32_t)q.pass * (uint32_t)per_pass[q.board];
+    if (need > 0u) {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(done + q.board, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins >= kQueueSpinLimit ||
+            __hip_atomic_load(error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+          if (lane == 0)
+            __hip_atomic_store(error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          return;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    int mine = -1;
+    for (int k = 0; k < q.nseg; ++k) {
+      const Segment sg = segs[q.seg_begin + k];
+      if (lane >= sg.lane0 && lane < sg.lane0 + sg.nlanes) mine = q.seg_begin + k;
+    }
+    const BoardDesc bd = boards[q.board];
+    const int j = q.pass;
+    const uint32_t* src = (j == 0) ? bd.src0 : bd.w[(j - 1 + bd.par) & 1];
+    uint32_t* dst = bd.w[(j + bd.par) & 1];
+    const int Tl = (j == bd.jshort) ? bd.Tshort : TM;
+    Lane L;
+    if (mine >= 0) {
+      const Segment sg = segs[mine];
+      lane_setup(L, src, dst, bd.R, bd.C, bd.D, sg.p0 + (lane - sg.lane0), lane - sg.lane0,
+                 sg.nlanes, sg.r0, sg.h, TM, Tl, true);
+    } else {
+      lane_setup(L, src, dst, bd.R, bd.C, bd.D, 0, 0, 1, 0, 1, TM, TM, false);
+    }
+    const bool shortp = Tl < TM;  // uniform: the item's one board and pass
+    if (q.flags & kItemAligned) {
+      if (shortp)
+        run_tile<TM, true, kGatherAligned, GOL_BATCH_PREFETCH, false>(L, q.h);
+      else
+        run_tile<TM, false, kGatherAligned, GOL_BATCH_PREFETCH, false>(L, q.h);
+    } else {
+      if (shortp)
+        run_tile<TM, true, kGatherTorus, GOL_BATCH_PREFETCH, false>(L, q.h);
+      else
+        run_tile<TM, false, kGatherTorus, GOL_BATCH_PREFETCH, false>(L, q.h);
+    }
+    // the stores of this item are complete and visible device-wide before
+    // the counter says so
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) __hip_atomic_fetch_add(done + q.board, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Layout conversion (byte boards of the host API) and normalising copies.
 // ---------------------------------------------------------------------------
 
@@ -1239,6 +1319,49 @@ hipError_t launch_batch_pass(int T, bool masked, const BoardDesc* boards, const 
     default: return hipErrorInvalidValue;
   }
 #undef GOL_LAUNCH_BATCH
+}
+
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t st);
+
+// Resident waves of the queue kernel on the current device (its occupancy
+// per compute unit times the compute units), or 0 if unknown.
+int batch_queue_waves(int T) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (T == 8) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_queue<8>, 64, 0);
+  if (T == 12) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_queue<12>, 64, 0);
+  if (T == 16) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batch_queue<16>, 64, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return per * cus;
+}
+
+// The persistent queue form: `waves` waves (the device's resident capacity
+// for the kernel) take the nitems items; ctl holds kQueueCtlHeader + boards
+// words, zeroed here first.
+hipError_t launch_batch_queue(int T, const BoardDesc* boards, const Segment* segs,
+                              const QueueItem* items, const int32_t* per_pass, int nitems,
+                              uint32_t* ctl, int nboards, int waves, hipStream_t st) {
+  hipError_t e = launch_fill_u32(ctl, (int64_t)kQueueCtlHeader + nboards, 0u, st);
+  if (e != hipSuccess || nitems <= 0) return e;
+  const int grid = waves < 1 ? 1 : waves;
+#define GOL_LAUNCH_QUEUE(TV)                                                                  \
+  case TV:                                                                                    \
+    hipLaunchKernelGGL(k_batch_queue<TV>, dim3(grid), dim3(64), 0, st, boards, segs, items,   \
+                       per_pass, nitems, ctl);                                                \
+    return hipGetLastError();
+  switch (T) {
+    GOL_LAUNCH_QUEUE(8)
+    GOL_LAUNCH_QUEUE(12)
+    GOL_LAUNCH_QUEUE(16)
+    default: return hipErrorInvalidValue;
+  }
+#undef GOL_LAUNCH_QUEUE
 }
 
 static int grid_for(int64_t n, int per_block) {

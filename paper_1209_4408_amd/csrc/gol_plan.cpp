@@ -467,4 +467,70 @@ int chunk_band_rows(const std::vector<std::pair<int64_t, int64_t>>& boards, int 
   return h;
 }
 
+bool build_queue_plan(const std::vector<BoardReq>& boards, int T, int band_rows, QueuePlan& qp,
+                      std::string& err) {
+  if (!(T == 8 || T == 12 || T == 16)) {
+    err = "the queue form runs 8, 12 or 16 generations per pass";
+    return false;
+  }
+  if (band_rows < 1 || band_rows > 65535) {
+    err = "band height out of range";
+    return false;
+  }
+  qp = QueuePlan();
+  qp.T = T;
+  const size_t n = boards.size();
+  qp.per_pass.assign(n, 0);
+  std::vector<int64_t> K(n, 0);
+  std::vector<int32_t> seg_base(n, 0), wave_base(n, 0);
+  std::vector<BoardTiles::Wave> waves;
+  int64_t Kmax = 0;
+  for (size_t b = 0; b < n; ++b) {
+    K[b] = (boards[b].generations + T - 1) / T;
+    Kmax = std::max(Kmax, K[b]);
+    if (K[b] == 0) continue;
+    BoardTiles t;
+    board_tiles(boards[b].rows, boards[b].cols, band_rows, t);
+    seg_base[b] = (int32_t)qp.segs.size();
+    wave_base[b] = (int32_t)waves.size();
+    for (Segment sg : t.segs) {
+      sg.board = (int32_t)b;
+      qp.segs.push_back(sg);
+    }
+    for (BoardTiles::Wave w : t.waves) {
+      w.seg_begin += seg_base[b];
+      waves.push_back(w);
+    }
+    qp.per_pass[b] = (int32_t)t.waves.size();
+  }
+  std::vector<int32_t> order;
+  for (size_t b = 0; b < n; ++b)
+    if (K[b] > 0) order.push_back((int32_t)b);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) {
+    return (double)boards[a].rows * boards[a].cols * boards[a].generations >
+           (double)boards[c].rows * boards[c].cols * boards[c].generations;
+  });
+  for (int64_t L = 0; L < Kmax; ++L)
+    for (int32_t b : order) {
+      if (L >= K[b]) continue;
+      const bool aligned = boards[b].cols % 32 == 0;
+      for (int32_t w = 0; w < qp.per_pass[b]; ++w) {
+        const BoardTiles::Wave& wv = waves[(size_t)wave_base[b] + w];
+        QueueItem it;
+        it.seg_begin = wv.seg_begin;
+        it.nseg = wv.nseg;
+        it.h = wv.h;
+        it.board = b;
+        it.pass = (int32_t)L;
+        it.flags = aligned ? kItemAligned : 0;
+        qp.items.push_back(it);
+      }
+    }
+  if (qp.items.size() > (size_t)INT32_MAX) {
+    err = "too many queue items";
+    return false;
+  }
+  return true;
+}
+
 }  // namespace gol

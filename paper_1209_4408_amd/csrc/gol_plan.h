@@ -115,6 +115,18 @@ bool build_chunk_plan(const std::vector<ChunkBoard>& boards, int T, HostPlan& pl
 int chunk_band_rows(const std::vector<std::pair<int64_t, int64_t>>& boards, int T, int nsimd,
                     int base);
 
+// The persistent work-queue form of a batch schedule (QueueItem): every
+// board tiled on its own (board_tiles at band_rows), its short pass first,
+// items queued pass by pass, boards within a pass longest work first.
+struct QueuePlan {
+  int T = 12;
+  std::vector<Segment> segs;
+  std::vector<QueueItem> items;
+  std::vector<int32_t> per_pass;  // items of each board per pass
+};
+bool build_queue_plan(const std::vector<BoardReq>& boards, int T, int band_rows, QueuePlan& qp,
+                      std::string& err);
+
 // Default band height for the single-board kernel: tall bands amortise the
 // 2T halo rows, but enough waves per SIMD are needed to hide latency, and the
 // wave total should not leave a few SIMDs one wave behind the rest.

@@ -159,3 +159,28 @@ def test_plan_tuned_choice_matches_oracle():
     assert cfg["t_block"] in (8, 12, 16) and cfg["band_rows"] in (48, 64, 96, 128)
     cfg = _run_plan_and_check(specs, 14, t_block=4)  # band tuned only
     assert cfg["t_block"] == 4 and cfg["band_rows"] in (48, 64, 96, 128)
+
+
+@pytest.mark.parametrize("T", [8, 12, 16])
+def test_queue_form_matches_oracle(T):
+    """The persistent work-queue form (one launch, per-board pass counters)
+    gives the oracle's boards, in place and with zero generations too, and
+    no wave gave up waiting."""
+    specs = _tall_mixed(90 + T, 40) + [(64, 64, 0), (3, 2000, 45), (200, 40, 70)]
+    boards, want = [], []
+    for i, (R, C, G) in enumerate(specs):
+        b = rand_bytes(5, i, R, C, 0.4)
+        d = to_dev(oracle.pack(b))
+        o = d if i % 5 == 0 else gol.empty_packed(R, C)  # every fifth in place
+        boards.append(gol.BatchBoard(d, o, R, C, G))
+        want.append(expect_words(b, G))
+    say("queue form T", T, len(boards))
+    p = gol.Plan(boards, t_block=T, band_rows=64, queue=True)
+    assert p.config()["layout"] == "queue"
+    p.run()
+    assert not p.queue_gave_up()
+    for i, bb in enumerate(boards):
+        got = from_dev(bb.d_out)
+        assert np.array_equal(got, want[i]), (T, i, specs[i],
+                                              first_diff(got, want[i], specs[i][1]))
+    p.close()
