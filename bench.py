@@ -318,7 +318,8 @@ def single_board(args, R, C, G, p, fixed_cfg="", compare_t1=False, cpu=True, cpu
                             launches_timed=args.steps * passes,
                             timed_as=f"runs of {g_main} generations ({passes} passes of {T})")
         roof = with_mix_ceiling(roof, cells * T / avg)
-        rec = f"traffic_{roof['kernel'].split('<')[0]}_{R}x{C}.json"
+        rec = (f"traffic_{roof['kernel'].split('<')[0]}_{R}x{C}"
+               f"_t{cfg['t_block']}_b{cfg['band_rows']}.json")
         roof["traffic"] = measured_traffic(rec, cfg)
         blk["roofline"] = roof
     else:
@@ -373,8 +374,8 @@ def batched(args, cpu=True):
     boards = [gol.BatchBoard(i, o, s.rows, s.cols, s.generations)
               for s, i, o in zip(specs, ins, outs)]
     st = torch.cuda.Stream()
-    log("creating the plan (tuned unless --t-block)")
-    plan = gol.Plan(boards, t_block=args.t_block)
+    log("creating the plan (tuned unless --t-block and --band-rows)")
+    plan = gol.Plan(boards, t_block=args.t_block, band_rows=args.band_rows)
     info = plan.info()
     pcfg = plan.config()
     T = pcfg["t_block"]
@@ -404,7 +405,9 @@ def batched(args, cpu=True):
     roof = alu_roofline(work, per, f"k_batch_pass<{T}, *>", launches=info["levels"],
                         note="algorithmic ops of the whole schedule over its device time "
                              "(two streams overlap, so per-launch durations are not "
-                             "separable)")
+                             "separable); traffic is HBM bytes per schedule")
+    roof["traffic"] = measured_traffic(f"traffic_k_batch_pass_{len(specs)}_boards.json",
+                                       {"t_block": T, "band_rows": pcfg["band_rows"]})
     blk = {"metric": "cell-updates/sec", "value": value, "unit": "cell-updates/s",
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
            "timed_s": wall, "device_s": dev, "dtype": "u32",
@@ -412,7 +415,7 @@ def batched(args, cpu=True):
                                   "p U(0.1, 0.6), generations U{10..1000}, one batched "
                                   "schedule", "boards": len(specs), "seed": SEED,
                       "t_block": T, "band_rows": pcfg["band_rows"],
-                      "tuned": not args.t_block, "cell_updates": work},
+                      "tuned": not (args.t_block and args.band_rows), "cell_updates": work},
            "roofline": roof, "plan": info, "queue_form": queue_blk}
     if not args.no_plain:
         log("plain per-board loop (library default configuration)")
@@ -1114,6 +1117,9 @@ def main():
     ap.add_argument("--plain-requests", type=int, default=4096)
     ap.add_argument("--boards", type=int, default=4096)
     ap.add_argument("--t-block", type=int, default=0)
+    ap.add_argument("--band-rows", type=int, default=0,
+                    help="batched workload: band height of the schedule (0 = tuned, with "
+                         "--t-block)")
     ap.add_argument("--compare-t1", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
