@@ -341,7 +341,7 @@ typedef struct {
   int64_t launches;        /* tile-pass launches queued */
   int64_t admitted;        /* requests admitted to the device */
   int64_t retired;         /* requests whose result copy was queued */
-  double plan_host_s;      /* host seconds spent building chunk schedules */
+  double plan_host_s;      /* host seconds spent building and launching chunk schedules */
   double device_busy_s;    /* device seconds of completed chunks (first to last launch) */
   double cell_updates;     /* cell updates queued */
   int64_t max_resident;    /* largest number of boards in one chunk */
@@ -352,6 +352,12 @@ typedef struct {
   int64_t last_chunk_generations; /* generations of the last chunk queued (at most) */
   int64_t last_band_rows;  /* band height of the last chunk's tiles */
   int64_t busy_band_rows;  /* band height of a chunk with many tiles (given or tuned) */
+  double admit_host_s;     /* host seconds the scheduler spent admitting requests */
+  double retire_host_s;    /* host seconds spent queueing result copies of finished boards */
+  double starved_s;        /* host-observed seconds with no chunk queued while boards had
+                              generations left (the device waited for the scheduler) */
+  double chunk_gap_s;      /* device seconds between one chunk's end and the next one's
+                              start (waiting for uploads, or for the scheduler) */
 } gol_serve_stats;
 int gol_serve_get_stats(const gol_server* srv, gol_serve_stats* out);
 int gol_serve_destroy(gol_server* srv);

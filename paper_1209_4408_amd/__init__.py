@@ -61,7 +61,9 @@ class ServeStats(ctypes.Structure):
                 ("mean_resident", ctypes.c_double), ("resident_bytes", ctypes.c_int64),
                 ("peak_resident_bytes", ctypes.c_int64), ("t_block", ctypes.c_int64),
                 ("last_chunk_generations", ctypes.c_int64), ("last_band_rows", ctypes.c_int64),
-                ("busy_band_rows", ctypes.c_int64)]
+                ("busy_band_rows", ctypes.c_int64), ("admit_host_s", ctypes.c_double),
+                ("retire_host_s", ctypes.c_double), ("starved_s", ctypes.c_double),
+                ("chunk_gap_s", ctypes.c_double)]
 
 
 class RequestInfo(ctypes.Structure):

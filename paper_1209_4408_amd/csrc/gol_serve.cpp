@@ -3,13 +3,16 @@
 // One scheduler thread per server.  Each tick it
 //   1. admits queued requests, oldest first, while their two device buffers
 //      fit the HBM budget: device memory and the host-to-device copy are
-//      queued on the upload stream, and the compute stream will wait for it;
-//   2. queues one chunk on the compute stream: every resident board advances
-//      min(chunk length, remaining) generations in one batched schedule of
-//      tile passes (boards admitted since the last tick join here);
+//      queued on the upload stream, followed by a marker;
+//   2. queues one chunk on the compute stream: every resident board whose
+//      upload marker the host has seen done advances min(chunk length,
+//      remaining) generations in one batched schedule of tile passes (so a
+//      chunk never stalls the device on an upload still in flight);
 //   3. for boards that finish in that chunk, queues the device-to-host copy
 //      (download stream, after the chunk) and the release of their buffers.
-// Board state stays in device memory between chunks.  Up to two chunks are
+// Submissions reach the scheduler through an inbox with its own lock, so a
+// client never waits for a scheduler tick.  Board state stays in device
+// memory between chunks.  Up to two chunks are
 // in flight, so the host prepares the next while the device runs the last.
 // Each board keeps its tiles from chunk to chunk (rebuilt only when the band
 // height changes), so a chunk's schedule is assembled in time linear in its
@@ -33,6 +36,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <chrono>
 #include <condition_variable>
@@ -70,9 +74,9 @@ class Exec {
   // identifies the block for host_free; cls 0 = plain malloc'd memory.
   virtual void* host_alloc(size_t bytes, size_t* cls) = 0;
   virtual void host_free(void* p, size_t cls) = 0;
-  // Host staging of a submitted board until its upload (plain memory: a
-  // burst of submissions pins nothing; the upload copies from it).
-  void* stage_alloc(size_t bytes, size_t* cls) {
+  // Host staging of a submitted board until its upload (called by the
+  // submitting thread, without the server lock): plain memory here.
+  virtual void* stage_alloc(size_t bytes, size_t* cls) {
     *cls = 0;
     return malloc(bytes ? bytes : 1);
   }
@@ -80,7 +84,12 @@ class Exec {
   virtual void board_free_after_copies(void* p) = 0;
   virtual void board_free_after_chunks(void* p) = 0;
   virtual int upload(void* dev, const void* host, size_t bytes) = 0;
-  virtual int chunks_wait_for_copies() = 0;
+  // A marker after the uploads queued so far (done() once they have run).
+  virtual int upload_mark(Token* mark) = 0;
+  // Chunks / result copies queued from now on come after the uploads before
+  // a marker (one the host has seen done: the device does not stall on it).
+  virtual int chunks_wait_for_upload(Token mark) = 0;
+  virtual int copies_wait_for_upload(Token mark) = 0;
   virtual int run_chunk(const std::vector<BoardDesc>& bd, const HostPlan& hp, Token* done) = 0;
   virtual int copies_wait_for(Token chunk) = 0;
   virtual int download(void* host, const void* dev, size_t bytes, Token* done) = 0;
@@ -88,6 +97,9 @@ class Exec {
   virtual int host_free_after(bool compute, void* pinned, size_t cls) = 0;
   virtual bool done(Token t) = 0;
   virtual double seconds(Token chunk) = 0;  // device time of a completed chunk
+  // Device time between the end of the chunk queued before this completed
+  // one and this one's start (0 if unknown).
+  virtual double gap_before(Token chunk) { (void)chunk; return 0.0; }
   virtual void release(Token t) = 0;
   virtual void reap() = 0;
   virtual void sync() = 0;
@@ -104,7 +116,7 @@ class HipExec : public Exec {
       for (hipEvent_t ev : {c.start, c.end, c.fork, c.join})
         if (ev) (void)hipEventDestroy(ev);
       if (c.meta) (void)hipFree(c.meta);
-      if (c.pin) (void)hipHostFree(c.pin);
+      if (c.pin) pinned_put(c.pin, c.pin_bytes);
     }
     for (Copy* c : copies_free_) {
       if (c->end) (void)hipEventDestroy(c->end);
@@ -150,12 +162,33 @@ class HipExec : public Exec {
     hipError_t e = hipSetDevice(dev_);
     return e == hipSuccess ? GOL_OK : hip_error(e, "server: hipSetDevice");
   }
-  void* host_alloc(size_t bytes, size_t* cls) override { return pinned_get(bytes, cls); }
+  void* host_alloc(size_t bytes, size_t* cls) override {
+    void* p = pinned_get(bytes, cls);
+    if (p) pinned_held_ += *cls;
+    return p;
+  }
+  // Submitted boards are staged in pinned blocks of the library's pool while
+  // the server holds less than kStagePinnedMax bytes of pinned staging, so
+  // their uploads are asynchronous copies that do not hold up the scheduler
+  // thread (an upload from pageable memory returns only once the runtime
+  // has staged it); beyond that, in plain memory.
+  void* stage_alloc(size_t bytes, size_t* cls) override {
+    size_t c = 4096;
+    while (c < bytes) c <<= 1;
+    if (pinned_held_.fetch_add(c) + c <= kStagePinnedMax) {
+      void* p = pinned_get(bytes, cls);
+      if (p) return p;
+    }
+    pinned_held_ -= c;
+    return Exec::stage_alloc(bytes, cls);
+  }
   void host_free(void* p, size_t cls) override {
-    if (cls == 0)
+    if (cls == 0) {
       free(p);
-    else
+    } else {
       pinned_put(p, cls);
+      pinned_held_ -= cls;
+    }
   }
   int board_alloc(size_t bytes, void** p) override {
     hipError_t e = hipMallocAsync(p, bytes, up_);
@@ -178,17 +211,24 @@ class HipExec : public Exec {
     hipError_t e = hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, up_);
     return e == hipSuccess ? GOL_OK : hip_error(e, "server: host-to-device copy");
   }
-  int chunks_wait_for_copies() override {
-    hipEvent_t ev = nullptr;
-    hipError_t e = event_get(&ev);
-    if (e == hipSuccess) e = hipEventRecord(ev, up_);
-    if (e == hipSuccess) e = hipStreamWaitEvent(compute_, ev, 0);
+  int upload_mark(Token* mark) override {
+    Copy* c = copy_get();
+    hipError_t e = c->end ? hipSuccess : event_get(&c->end);
+    if (e == hipSuccess) e = hipEventRecord(c->end, up_);
     if (e != hipSuccess) {
-      if (ev) events_.push_back(ev);
-      return hip_error(e, "server: admission event");
+      copies_free_.push_back(c);
+      return hip_error(e, "server: upload marker");
     }
-    pending_.push_back(Pending{ev, nullptr, 0, nullptr});
+    *mark = c;
     return GOL_OK;
+  }
+  int chunks_wait_for_upload(Token mark) override {
+    hipError_t e = hipStreamWaitEvent(compute_, ((Copy*)mark)->end, 0);
+    return e == hipSuccess ? GOL_OK : hip_error(e, "server: stream wait");
+  }
+  int copies_wait_for_upload(Token mark) override {
+    hipError_t e = hipStreamWaitEvent(down_, ((Copy*)mark)->end, 0);
+    return e == hipSuccess ? GOL_OK : hip_error(e, "server: stream wait");
   }
   // A chunk's tables go through the next of a ring of slots, each keeping
   // its pinned staging, its device table block and its four events from one
@@ -201,23 +241,26 @@ class HipExec : public Exec {
     const size_t oi = os + al(hp.segs.size() * sizeof(Segment));
     const size_t mb = oi + al(hp.items.size() * sizeof(WaveItem));
     Slot& c = slots_[next_slot_];
+    c.index = next_slot_;
     next_slot_ = (next_slot_ + 1) % kSlots;
     hipError_t e = hipSuccess;
     if (c.busy) e = hipEventSynchronize(c.end);  // not reached while two chunks at most are queued
     c.busy = false;
     if (e == hipSuccess && c.pin_bytes < mb) {
-      if (c.pin) (void)hipHostFree(c.pin);
-      c.pin = nullptr;
-      c.pin_bytes = 0;
-      const size_t want = std::max(mb + mb / 2, (size_t)1 << 16);
-      e = hipHostMalloc(&c.pin, want, hipHostMallocDefault);
-      if (e == hipSuccess) c.pin_bytes = want;
+      // from the library's pinned pool: freeing page-locked memory waits for
+      // the device, which would drain the chunks in flight
+      if (c.pin) pinned_put(c.pin, c.pin_bytes);
+      c.pin = pinned_get(std::max(2 * mb, kSlotMinBytes), &c.pin_bytes);
+      if (!c.pin) {
+        c.pin_bytes = 0;
+        e = hipErrorOutOfMemory;
+      }
     }
     if (e == hipSuccess && c.meta_bytes < mb) {
       if (c.meta) (void)hipFreeAsync(c.meta, compute_);
       c.meta = nullptr;
       c.meta_bytes = 0;
-      const size_t want = std::max(mb + mb / 2, (size_t)1 << 16);
+      const size_t want = std::max(2 * mb, kSlotMinBytes);
       e = hipMallocAsync(&c.meta, want, compute_);
       if (e == hipSuccess) c.meta_bytes = want;
     }
@@ -235,6 +278,7 @@ class HipExec : public Exec {
     if (e == hipSuccess) e = hipEventRecord(c.end, compute_);
     if (e != hipSuccess) return hip_error(e, "server: chunk launch");
     c.busy = true;
+    c.seq = ++seq_;
     *done = &c;
     return GOL_OK;
   }
@@ -243,13 +287,7 @@ class HipExec : public Exec {
     return e == hipSuccess ? GOL_OK : hip_error(e, "server: stream wait");
   }
   int download(void* host, const void* dev, size_t bytes, Token* done) override {
-    Copy* c = nullptr;
-    if (!copies_free_.empty()) {
-      c = copies_free_.back();
-      copies_free_.pop_back();
-    } else {
-      c = new Copy();
-    }
+    Copy* c = copy_get();
     hipError_t e = hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, down_);
     if (e == hipSuccess && !c->end) e = event_get(&c->end);
     if (e == hipSuccess) e = hipEventRecord(c->end, down_);
@@ -257,7 +295,6 @@ class HipExec : public Exec {
       copies_free_.push_back(c);
       return hip_error(e, "server: result copy");
     }
-    c->kind = 1;
     *done = c;
     return GOL_OK;
   }
@@ -278,8 +315,30 @@ class HipExec : public Exec {
     if (g->kind != 0) return 0.0;
     const Slot* c = (const Slot*)t;
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, c->start, c->end) != hipSuccess) return 0.0;
+    if (hipEventElapsedTime(&ms, c->start, c->end) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0.0;
+    }
     return ms * 1e-3;
+  }
+  // The slot before a chunk's in the ring held the chunk queued before it
+  // (its events are reused only by the chunk after next, which is queued
+  // after this one completes).
+  double gap_before(Token t) override {
+    const Tagged* g = (const Tagged*)t;
+    if (g->kind != 0) return 0.0;
+    const Slot* c = (const Slot*)t;
+    const Slot& p = slots_[(c->index + kSlots - 1) % kSlots];
+    if (p.seq + 1 != c->seq) return 0.0;
+    // both intervals from the earlier chunk's start event (the start-to-end
+    // pair is the one seconds() reads); a failed query leaves no error behind
+    float to_start = 0.f, to_end = 0.f;
+    if (hipEventElapsedTime(&to_start, p.start, c->start) != hipSuccess ||
+        hipEventElapsedTime(&to_end, p.start, p.end) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0.0;
+    }
+    return to_start > to_end ? (to_start - to_end) * 1e-3 : 0.0;
   }
   void release(Token t) override {
     Tagged* g = (Tagged*)t;
@@ -312,7 +371,7 @@ class HipExec : public Exec {
   }
 
  private:
-  // Tokens: a chunk's slot (kind 0) or a result copy (kind 1).
+  // Tokens: a chunk's slot (kind 0), or a result copy or upload marker (kind 1).
   struct Tagged {
     int kind = 0;
   };
@@ -323,10 +382,23 @@ class HipExec : public Exec {
     void* meta = nullptr;
     size_t meta_bytes = 0;
     bool busy = false;
+    int index = 0;     // position in the ring
+    uint64_t seq = 0;  // order in which chunks were queued (1, 2, ...)
   };
   struct Copy : Tagged {
     hipEvent_t end = nullptr;  // kept with the record for its next use
   };
+  Copy* copy_get() {
+    Copy* c = nullptr;
+    if (copies_free_.empty()) {
+      c = new Copy();
+    } else {
+      c = copies_free_.back();
+      copies_free_.pop_back();
+    }
+    c->kind = 1;
+    return c;
+  }
   // Waits on the host for an event: then the pinned block returns to the
   // pool, or the device block is freed on the upload stream.
   struct Pending {
@@ -349,6 +421,10 @@ class HipExec : public Exec {
     (void)hipFreeAsync(p, up_);
   }
   static constexpr int kSlots = 3;
+  // Smallest table block of a slot (pinned and device): a chunk over a few
+  // thousand boards fits, so a busy server does not grow its tables (a new
+  // device block is a stream-ordered allocation the compute stream waits on).
+  static constexpr size_t kSlotMinBytes = (size_t)4 << 20;
   hipEvent_t end_of(Token t) const {
     const Tagged* g = (const Tagged*)t;
     return g->kind == 0 ? ((const Slot*)t)->end : ((const Copy*)t)->end;
@@ -372,9 +448,12 @@ class HipExec : public Exec {
   hipStream_t compute2_ = nullptr;  // the late group of each chunk's schedule
   Slot slots_[kSlots];
   int next_slot_ = 0;
+  uint64_t seq_ = 0;
   std::vector<Copy*> copies_free_;
   std::vector<hipEvent_t> events_;  // free events
   std::vector<Pending> pending_;    // touched by the scheduler thread under the server lock
+  static constexpr size_t kStagePinnedMax = (size_t)1 << 30;
+  std::atomic<size_t> pinned_held_{0};  // pinned staging (inputs and results) held now
 };
 
 // Boards in host memory, every operation complete on return (see the file
@@ -404,7 +483,12 @@ class HostExec : public Exec {
     memcpy(dev, host, bytes);
     return GOL_OK;
   }
-  int chunks_wait_for_copies() override { return GOL_OK; }
+  int upload_mark(Token* mark) override {
+    *mark = &token_;
+    return GOL_OK;
+  }
+  int chunks_wait_for_upload(Token) override { return GOL_OK; }
+  int copies_wait_for_upload(Token) override { return GOL_OK; }
   // Replays the chunk's schedule as the device would run it: level by level,
   // the early group's waves then the late group's, each segment taking the
   // pass of its board that the level runs (the buffer it reads and writes,
@@ -498,6 +582,7 @@ struct Request {
   bool cancel = false;
   bool retiring = false;       // final copy queued
   Token out_done = nullptr;    // device-to-host copy of the result done
+  uint64_t mark = 0;           // upload marker its input copy precedes
   BoardTiles tiles;            // the board's tiles at the band height last used
   double t_submit = 0, t_admit = 0, t_done = 0;
   std::string err;
@@ -517,7 +602,18 @@ struct Server {
   bool stop = false;
   bool failed = false;
   std::string fail_msg;
-  uint64_t next_ticket = 1;
+
+  // Submissions land in the inbox under in_mu, never under mu, which a busy
+  // scheduler holds for whole ticks; whoever holds mu moves them into reqs
+  // and the admission queue (drain_inbox).  Before an idle wait the
+  // scheduler sets `sleeping` and rechecks inbox_n; a submitter that finds
+  // `sleeping` set takes mu to wake it, so no submission waits out a sleep.
+  std::mutex in_mu;
+  std::vector<std::unique_ptr<Request>> inbox;  // under in_mu
+  uint64_t next_ticket = 1;                     // under in_mu
+  std::atomic<int64_t> inbox_n{0};
+  std::atomic<bool> sleeping{false};
+  std::atomic<bool> failed_seen{false};  // S.failed, readable without mu
   std::deque<uint64_t> queue;                      // admission order
   std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
   std::vector<uint64_t> resident;                  // admitted, not yet retired
@@ -528,6 +624,19 @@ struct Server {
   int T = 16;                                      // generations per pass (resolved)
   int band = 96;                                   // band height of a busy chunk (resolved)
   double rate = 0.0;  // cell updates per device second of completed chunks (running mean)
+  double t_starved = -1.0;  // when the last queued chunk was seen done with work left over
+
+  // Upload markers, one per admitting tick, numbered 1, 2, ...: a board
+  // joins chunks (or, with no generations, retires) once the host has seen
+  // its marker done, so a chunk never waits on the device for an upload
+  // still in flight; the device-side wait on a done marker keeps the copy
+  // ordered before the kernels that read it.
+  std::deque<std::pair<uint64_t, Token>> marks;  // issued, not yet seen done
+  uint64_t mark_seq = 0;       // last issued
+  uint64_t uploaded = 0;       // last seen done
+  Token uploaded_mark = nullptr;  // its marker (kept for the waits below)
+  uint64_t chunks_after = 0;   // chunks queued from now on follow uploads up to this marker
+  uint64_t copies_after = 0;   // result copies likewise
   gol_serve_stats stats{};
   std::thread th;
 
@@ -539,6 +648,7 @@ struct Server {
 static void fail_all(Server& S, const std::string& msg) {
   // caller holds S.mu
   S.failed = true;
+  S.failed_seen = true;
   S.fail_msg = msg;
   for (auto& kv : S.reqs) {
     Request& r = *kv.second;
@@ -550,19 +660,65 @@ static void fail_all(Server& S, const std::string& msg) {
   S.cv_done.notify_all();
 }
 
+// Submissions from the inbox into reqs and the admission queue, in ticket
+// order.  Caller holds S.mu.
+static void drain_inbox(Server& S) {
+  if (S.inbox_n.load() == 0) return;
+  std::vector<std::unique_ptr<Request>> got;
+  {
+    std::lock_guard<std::mutex> g(S.in_mu);
+    got.swap(S.inbox);
+    S.inbox_n = 0;
+  }
+  for (auto& r : got) {
+    if (S.failed) {
+      r->state = State::Failed;
+      r->err = S.fail_msg;
+      if (r->pin_in) S.exec->host_free(r->pin_in, r->pin_in_cls);
+      r->pin_in = nullptr;
+    } else {
+      S.queue.push_back(r->ticket);
+    }
+    const uint64_t t = r->ticket;
+    S.reqs.emplace(t, std::move(r));
+  }
+  if (S.failed) S.cv_done.notify_all();
+}
+
 static void reap(Server& S) {
   S.exec->reap();
+  while (!S.marks.empty() && S.exec->done(S.marks.front().second)) {
+    if (S.uploaded_mark) S.exec->release(S.uploaded_mark);
+    S.uploaded = S.marks.front().first;
+    S.uploaded_mark = S.marks.front().second;
+    S.marks.pop_front();
+  }
   while (!S.chunks.empty() && S.exec->done(S.chunks.front())) {
     const double secs = S.exec->seconds(S.chunks.front());
     const double cu = S.chunk_cu.front();
     S.stats.device_busy_s += secs;
+    S.stats.chunk_gap_s += S.exec->gap_before(S.chunks.front());
     if (secs > 0.0 && cu > 0.0)
       S.rate = S.rate > 0.0 ? 0.75 * S.rate + 0.25 * (cu / secs) : cu / secs;
     S.exec->release(S.chunks.front());
     S.chunks.pop_front();
     S.chunk_cu.pop_front();
+    if (S.chunks.empty() && S.t_starved < 0.0) {
+      bool work = !S.queue.empty();
+      for (size_t i = 0; !work && i < S.resident.size(); ++i) {
+        const Request& r = *S.reqs[S.resident[i]];
+        work = !r.cancel && !r.retiring && r.queued_gens < r.gens;
+      }
+      if (work) S.t_starved = S.now();
+    }
   }
 }
+
+// Host seconds one scheduler tick spends admitting requests before it goes
+// on to queue chunks and retire boards: a device with fewer than two chunks
+// queued gets the next one sooner.
+constexpr double kAdmitSliceHungry = 0.0003;
+constexpr double kAdmitSlice = 0.001;
 
 // Device time a chunk of an automatic length aims at: long enough that its
 // launches and host work are small beside it, short enough that a request
@@ -619,6 +775,7 @@ static int admit(Server& S, Request& r) {
   r.d_buf[1] = (uint64_t*)p1;
   r.cur = 0;
   rc = S.exec->upload(p0, r.pin_in, r.bytes);
+  r.mark = S.mark_seq + 1;  // the marker queued after this tick's admissions
   if (!rc) rc = S.exec->host_free_after(false, r.pin_in, r.pin_in_cls);
   if (rc) return rc == GOL_ENOMEM ? GOL_EDEVICE : rc;
   r.pin_in = nullptr;
@@ -636,7 +793,8 @@ static int queue_chunk(Server& S, std::vector<uint64_t>& retire_now) {
   std::vector<Request*> act;
   for (uint64_t t : S.resident) {
     Request& r = *S.reqs[t];
-    if (!r.cancel && !r.retiring && r.queued_gens < r.gens) act.push_back(&r);
+    if (!r.cancel && !r.retiring && r.queued_gens < r.gens && r.mark <= S.uploaded)
+      act.push_back(&r);
   }
   if (act.empty()) return GOL_OK;
   const auto t_plan0 = std::chrono::steady_clock::now();
@@ -673,12 +831,24 @@ static int queue_chunk(Server& S, std::vector<uint64_t>& retire_now) {
     d.w[1] = (uint32_t*)r.d_buf[r.cur];
     d.par = 0;  // pass j writes w[j & 1]; the result lands in w[(K - 1) & 1]
   }
+  Token done = nullptr;
+  int rc = GOL_OK;
+  bool fresh = false;
+  for (const Request* r : act) fresh = fresh || r->mark > S.chunks_after;
+  if (fresh) {
+    rc = S.exec->chunks_wait_for_upload(S.uploaded_mark);
+    if (rc) return rc;
+    S.chunks_after = S.uploaded;
+  }
+  rc = S.exec->run_chunk(bd, hp, &done);
   S.stats.plan_host_s +=
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t_plan0).count();
-  Token done = nullptr;
-  int rc = S.exec->run_chunk(bd, hp, &done);
   if (rc) return rc;
   S.chunks.push_back(done);
+  if (S.t_starved >= 0.0) {
+    S.stats.starved_s += S.now() - S.t_starved;
+    S.t_starved = -1.0;
+  }
   S.chunk_cu.push_back(hp.cell_updates);
   S.stats.chunks += 1;
   S.stats.last_chunk_generations = gchunk;
@@ -733,6 +903,7 @@ static void scheduler(Server* Sp) {
   }
   std::unique_lock<std::mutex> lk(S.mu);
   while (true) {
+    drain_inbox(S);
     reap(S);
     finish_copies(S);
     if (S.stop) break;
@@ -754,9 +925,18 @@ static void scheduler(Server* Sp) {
         ++i;
       }
     }
-    // admission, oldest first, under the budget and the resident cap
+    // admission, oldest first, under the budget and the resident cap, for at
+    // most a slice of host time per tick (shorter while the device has fewer
+    // than two chunks to run), so that a burst of submissions is admitted
+    // over several ticks between which chunks keep the device busy
     bool admitted = false;
+    const auto t_admit0 = std::chrono::steady_clock::now();
+    const double slice = S.chunks.size() < 2 ? kAdmitSliceHungry : kAdmitSlice;
     while (!S.queue.empty()) {
+      if (admitted && !S.resident.empty() &&
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t_admit0).count() >
+              slice)
+        break;
       Request& r = *S.reqs[S.queue.front()];
       if (r.cancel) {
         r.state = State::Cancelled;
@@ -795,23 +975,36 @@ static void scheduler(Server* Sp) {
       admitted = true;
       did = true;
     }
-    // the next chunk reads what the copy queue wrote
-    if (admitted && rc == GOL_OK) rc = S.exec->chunks_wait_for_copies();
+    S.stats.admit_host_s +=
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_admit0).count();
+    // a marker after this tick's uploads
+    if (admitted && rc == GOL_OK) {
+      Token t = nullptr;
+      rc = S.exec->upload_mark(&t);
+      if (rc == GOL_OK) S.marks.emplace_back(++S.mark_seq, t);
+    }
     // one chunk if fewer than two are in flight
     if (rc == GOL_OK && S.chunks.size() < 2) {
       std::vector<uint64_t> retire_now;
       rc = queue_chunk(S, retire_now);
+      const auto t_ret0 = std::chrono::steady_clock::now();
       for (uint64_t t : retire_now) {
         if (rc) break;
         rc = queue_retire(S, *S.reqs[t]);
       }
+      S.stats.retire_host_s +=
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t_ret0).count();
       if (!retire_now.empty()) did = true;
     }
     // boards with zero generations retire without a chunk
     for (uint64_t t : S.resident) {
       Request& r = *S.reqs[t];
-      if (rc == GOL_OK && !r.retiring && !r.cancel && r.gens == 0) {
-        rc = queue_retire(S, r);
+      if (rc == GOL_OK && !r.retiring && !r.cancel && r.gens == 0 && r.mark <= S.uploaded) {
+        if (r.mark > S.copies_after) {
+          rc = S.exec->copies_wait_for_upload(S.uploaded_mark);
+          S.copies_after = S.uploaded;
+        }
+        if (rc == GOL_OK) rc = queue_retire(S, r);
         did = true;
       }
     }
@@ -829,10 +1022,14 @@ static void scheduler(Server* Sp) {
       bool copies = false;
       for (auto& kv : S.reqs)
         if (kv.second->retiring && kv.second->state == State::Resident) copies = true;
-      if (!S.chunks.empty() || copies)
-        S.cv_work.wait_for(lk, std::chrono::microseconds(50));
-      else
-        S.cv_work.wait_for(lk, std::chrono::milliseconds(20));
+      S.sleeping = true;
+      if (S.inbox_n.load() == 0) {
+        if (!S.chunks.empty() || copies || !S.marks.empty())
+          S.cv_work.wait_for(lk, std::chrono::microseconds(50));
+        else
+          S.cv_work.wait_for(lk, std::chrono::milliseconds(20));
+      }
+      S.sleeping = false;
     }
   }
 }
@@ -970,20 +1167,24 @@ int gol_serve_submit(gol_server* srv, const uint64_t* host_packed, int64_t rows,
       uint64_t* last = (uint64_t*)r->pin_in + (W - 1);
       for (int64_t i = 0; i < rows; ++i) last[i * W] &= keep;
     }
-    std::lock_guard<std::mutex> lk(S.mu);
-    if (S.failed) {
+    if (S.failed_seen) {
       S.exec->host_free(r->pin_in, r->pin_in_cls);
+      std::lock_guard<std::mutex> lk(S.mu);
       return set_error(GOL_EDEVICE, "server failed: %s", S.fail_msg.c_str());
     }
+    std::lock_guard<std::mutex> g(S.in_mu);
     r->ticket = S.next_ticket++;
     r->t_submit = S.now();
     *ticket = r->ticket;
-    S.queue.push_back(r->ticket);
-    S.reqs.emplace(r->ticket, std::move(r));
+    S.inbox.push_back(std::move(r));
+    S.inbox_n += 1;
   } catch (const std::bad_alloc&) {
     return set_error(GOL_ENOMEM, "host allocation failed");
   }
-  S.cv_work.notify_one();
+  if (S.sleeping.load()) {
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.cv_work.notify_one();
+  }
   return GOL_OK;
 }
 
@@ -1022,6 +1223,7 @@ int gol_serve_poll(gol_server* srv, uint64_t ticket, uint64_t* host_out, gol_req
   if (!srv) return set_error(GOL_EINVAL, "null server");
   Server& S = srv->S;
   std::unique_lock<std::mutex> lk(S.mu);
+  drain_inbox(S);
   finish_copies(S);
   return take_result(S, ticket, host_out, info, lk);
 }
@@ -1030,6 +1232,7 @@ int gol_serve_wait(gol_server* srv, uint64_t ticket, uint64_t* host_out, gol_req
   if (!srv) return set_error(GOL_EINVAL, "null server");
   Server& S = srv->S;
   std::unique_lock<std::mutex> lk(S.mu);
+  drain_inbox(S);
   while (true) {
     auto it = S.reqs.find(ticket);
     if (it == S.reqs.end()) break;
@@ -1045,6 +1248,7 @@ int gol_serve_cancel(gol_server* srv, uint64_t ticket) {
   if (!srv) return set_error(GOL_EINVAL, "null server");
   Server& S = srv->S;
   std::lock_guard<std::mutex> lk(S.mu);
+  drain_inbox(S);
   auto it = S.reqs.find(ticket);
   if (it == S.reqs.end())
     return set_error(GOL_ENOTFOUND, "unknown or retired ticket %llu", (unsigned long long)ticket);
@@ -1075,10 +1279,18 @@ int gol_serve_destroy(gol_server* srv) {
   }
   S.cv_work.notify_all();
   if (S.th.joinable()) S.th.join();
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    drain_inbox(S);
+  }
   S.exec->sync();
   reap(S);
   for (Token t : S.chunks) S.exec->release(t);
   S.chunks.clear();
+  for (auto& m : S.marks) S.exec->release(m.second);
+  S.marks.clear();
+  if (S.uploaded_mark) S.exec->release(S.uploaded_mark);
+  S.uploaded_mark = nullptr;
   for (auto& kv : S.reqs) {
     Request& r = *kv.second;
     if (r.out_done) S.exec->release(r.out_done);
