@@ -329,11 +329,11 @@ def single_board(args, R, C, G, p, fixed_cfg="", compare_t1=False, cpu=True, cpu
         log(f"timing {R}x{C}x{G} one generation per launch: {n1} steps")
         wall1, dev1 = timed_region(torch, lambda: gol.step_packed(d_in, R, C, G, d_out,
                                                                   t_block=1), n1, 1)
+        k1 = "k_step_t1" if C % 128 == 0 else f"k_board_pass<1, 3, {1 if C % 32 == 0 else 0}>"
+        roof1 = hbm_roofline(cells, dev1 / (n1 * G), k1)
+        roof1["traffic"] = measured_traffic(f"traffic_{k1.split('<')[0]}_{R}x{C}.json")
         blk["t1"] = {"value": cells * G * n1 / wall1, "unit": "cell-updates/s", "steps": n1,
-                     "timed_s": wall1,
-                     "roofline": hbm_roofline(cells, dev1 / (n1 * G),
-                                              "k_step_t1" if C % 128 == 0 else
-                                              f"k_board_pass<1, 3, {1 if C % 32 == 0 else 0}>")}
+                     "timed_s": wall1, "roofline": roof1}
         blk["speedup_vs_t1"] = value / blk["t1"]["value"]
     del d_in, d_out
     torch.cuda.empty_cache()
