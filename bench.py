@@ -285,10 +285,9 @@ def single_board(args, R, C, G, p, fixed_cfg="", compare_t1=False, cpu=True, cpu
     import torch
     import paper_1209_4408_amd as gol
     import seeded_inputs
-    log(f"generating {R}x{C} board p={p}")
-    w = seeded_inputs.board_packed(SEED, 0, R, C, p)
-    d_in = torch.from_numpy(w.view(np.int64)).cuda()
-    del w
+    log(f"generating {R}x{C} board p={p} on the device")
+    d_in = torch.empty(R * ((C + 63) // 64), dtype=torch.int64, device="cuda")
+    seeded_inputs.board_packed_device(SEED, 0, R, C, p, d_in)
     d_out = torch.empty_like(d_in)
     torch.cuda.synchronize()
     cfg = resolve_config(gol, R, C, args, fixed_cfg)

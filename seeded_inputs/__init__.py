@@ -3,7 +3,8 @@
 This module serves both the oracle side (tests) and the GPU side (tests, bench)
 and holds none of the Life arithmetic: it only draws boards and workload
 parameters.  Cells come from the counter-based SplitMix64 generator in
-``gen.c`` (see its header for the exact definition); workload parameters of the
+``gen.c`` (see its header for the exact definition; ``gen_device.hip`` draws
+the same cells straight into device memory); workload parameters of the
 batched and served mixes come from ``numpy.random.default_rng(seed)``.
 
 Workloads (synthetic stand-ins for the paper's drawn initial figures, which the
@@ -26,17 +27,42 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gen.c")
 _LIB = os.path.join(_HERE, "libseeded_inputs.so")
+_DEV_SRC = os.path.join(_HERE, "gen_device.hip")
+_DEV_LIB = os.path.join(_HERE, "libseeded_inputs_device.so")
+_HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 _lib = None
+_dev_lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile gen.c into a shared library next to it."""
+    """Compile gen.c (host) and gen_device.hip (gfx950) into shared libraries
+    next to them."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", _SRC,
                                "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(_DEV_LIB):
+        tmp = _DEV_LIB + ".tmp"
+        subprocess.check_call([_HIPCC, "-O3", "-shared", "-fPIC", "--offload-arch=gfx950",
+                               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                               _DEV_SRC, "-o", tmp])
+        os.replace(tmp, _DEV_LIB)
     return _LIB
+
+
+def _load_device():
+    global _dev_lib
+    if _dev_lib is None:
+        if not os.path.exists(_DEV_LIB):
+            raise RuntimeError(f"{_DEV_LIB} is missing: run seeded_inputs.build() first")
+        lib = ctypes.CDLL(_DEV_LIB)
+        lib.si_gen_packed_device.restype = ctypes.c_int
+        lib.si_gen_packed_device.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
+                                             ctypes.c_int64, ctypes.c_double, ctypes.c_void_p,
+                                             ctypes.c_void_p]
+        _dev_lib = lib
+    return _dev_lib
 
 
 def _load():
@@ -93,6 +119,24 @@ def board_packed(seed: int, board_id: int, rows: int, cols: int, p: float,
     rc = _load().si_gen_packed(seed, board_id, rows, cols, float(p), out.ctypes.data)
     if rc != 0:
         raise ValueError("invalid board size")
+    return out
+
+
+def board_packed_device(seed: int, board_id: int, rows: int, cols: int, p: float, out):
+    """The board of board_packed, drawn on the device into `out`: a contiguous
+    int64 / uint64 torch tensor on a GPU with rows * ceil(cols/64) elements,
+    on the current stream (asynchronous).  Returns `out`."""
+    import torch
+    w = words_per_row(cols)
+    if not (out.is_cuda and out.is_contiguous() and out.dtype in (torch.int64, torch.uint64)
+            and out.numel() == rows * w):
+        raise ValueError("out must be a contiguous 64-bit GPU tensor of rows * words_per_row "
+                         "elements")
+    rc = _load_device().si_gen_packed_device(seed, board_id, rows, cols, float(p),
+                                             out.data_ptr(),
+                                             torch.cuda.current_stream().cuda_stream)
+    if rc != 0:
+        raise ValueError("invalid board size" if rc == -1 else "device generation failed")
     return out
 
 

@@ -75,3 +75,10 @@ def test_serve_specs_poisson():
     gaps = np.diff(np.concatenate([[0.0], t]))
     assert abs(gaps.mean() - 1 / 500.0) < 0.1 / 500.0
     assert all(32 <= s.rows <= 8192 and 1 <= s.generations <= 10000 for s in specs)
+
+
+def test_device_generator_library_exports_its_entry_point():
+    """The device form (gen_device.hip) loads on a machine without a GPU and
+    exports its one entry point; its output is checked on the GPU."""
+    lib = seeded_inputs._load_device()
+    assert hasattr(lib, "si_gen_packed_device")
