@@ -364,3 +364,43 @@ def test_many_threads_submitting():
             th.join()
         assert srv.host_peak_bytes() <= 8 * 2 * bytes_of(R, C)
     assert not errors, errors
+
+
+def test_submissions_from_threads_while_the_scheduler_is_busy():
+    """Submissions go through the inbox while the scheduler runs chunks: every
+    ticket is distinct, can be waited on at once from another thread, and its
+    result is right; the time counters are non-negative and the host
+    executor reports no device time between chunks."""
+    import threading
+    with gol.Server(hbm_budget_bytes=1 << 26, chunk_generations=8, host_executor=True) as srv:
+        boards = {}
+        lock = threading.Lock()
+        errors = []
+
+        def client(k):
+            try:
+                for i in range(25):
+                    R, C, G = 5 + (i % 7), 40 + 13 * k, (i * 5) % 37
+                    w = board(100 * k + i, R, C)
+                    t = srv.submit(w, R, C, G)
+                    out = np.zeros_like(w)
+                    srv.wait(t, out)
+                    assert np.array_equal(out, expect(w, G)), (k, i)
+                    with lock:
+                        assert t not in boards
+                        boards[t] = (R, C, G)
+            except Exception as e:  # surfaced below
+                errors.append(e)
+
+        th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        assert not errors, errors
+        assert len(boards) == 100
+        st = srv.stats()
+    for k in ("admit_host_s", "retire_host_s", "plan_host_s", "starved_s", "chunk_gap_s"):
+        assert st[k] >= 0.0, (k, st[k])
+    assert st["chunk_gap_s"] == 0.0
+    assert st["admitted"] == 100 and st["retired"] == 100
