@@ -306,7 +306,9 @@ typedef struct gol_serve_config {
                                   or 16 x 64, 96 or 128 rows, whichever runs a stand-in
                                   resident set fastest: square boards of 512 to 8192 a side,
                                   the same cells at each size, 48 generations; with t_block
-                                  given only the band height is timed).  A chunk whose tiles
+                                  given only the band height is timed; the choice is kept for
+                                  the process's later servers on the same device and t_block,
+                                  which start without timing).  A chunk whose tiles
                                   give fewer than two waves per SIMD halves the band height
                                   (not below 32 rows or t_block) until they do. */
 } gol_serve_config;

@@ -1034,7 +1034,7 @@ static void scheduler(Server* Sp) {
   }
 }
 
-// The pass length and band height of every chunk, timed once at creation on
+// The pass length and band height of every chunk, timed at the first creation on
 // a resident set standing in for a busy server: square boards of 512 to
 // 8192 cells a side, four times as many of each size as of the next larger
 // (so every size holds the same cells: 1 of 8192^2 ... 256 of 512^2, 3.4e8
@@ -1042,7 +1042,19 @@ static void scheduler(Server* Sp) {
 // t_block 8, 12, 16 (or the given one) and band heights 64, 96, 128; the
 // fastest pair serves every chunk (a chunk with few tiles shortens the band,
 // see chunk_band_rows).
+// The choice is kept per device and given t_block for the process's later
+// servers.
 static int tune_served(int device, int T_fixed, int* T_out, int* band_out) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, std::pair<int, int>> chosen;
+  std::lock_guard<std::mutex> lk(mu);
+  const auto key = std::make_pair(device, T_fixed);
+  const auto it = chosen.find(key);
+  if (it != chosen.end()) {
+    *T_out = it->second.first;
+    *band_out = it->second.second;
+    return GOL_OK;
+  }
   int prev = 0;
   (void)hipGetDevice(&prev);
   hipError_t e = hipSetDevice(device);
@@ -1053,6 +1065,7 @@ static int tune_served(int device, int T_fixed, int* T_out, int* band_out) {
   const std::vector<int> Ts = T_fixed ? std::vector<int>{T_fixed} : std::vector<int>{8, 12, 16};
   const int rc = tune_batch(set, Ts, {64, 96, 128}, T_out, band_out, nullptr);
   (void)hipSetDevice(prev);
+  if (rc == GOL_OK) chosen[key] = std::make_pair(*T_out, *band_out);
   return rc;
 }
 
