@@ -571,7 +571,7 @@ struct Request {
   uint64_t ticket = 0;
   int64_t rows = 0, cols = 0, W = 0, gens = 0;
   size_t bytes = 0;
-  void* pin_in = nullptr;      // staged input (plain memory) until its upload
+  void* pin_in = nullptr;      // staged input (pinned or plain) until its upload
   size_t pin_in_cls = 0;
   void* pin_out = nullptr;
   size_t pin_out_cls = 0;
