@@ -7,8 +7,8 @@
 // branches), so zeroed scratch boards time it faithfully.  Candidates: both
 // layouts (one band per wave; two bands per wave sharing an edge, where the
 // board allows it), T in {8, 12, 16} with the prefetch distance that suits
-// it, and band heights that put about k waves on each SIMD for k in
-// {2, 3, 4, 6, 8}.  Results live in a per-process table keyed by (device,
+// it (for one band per wave at T = 16 also a shorter one), and band heights
+// that put about k waves on each SIMD for k in {2, 3, 4, 6, 8, 10, 12}.  Results live in a per-process table keyed by (device,
 // rows, cols); when GOL_AUTOTUNE_CACHE names a file, choices are also
 // appended there and read back on first use.
 #include <hip/hip_runtime.h>
@@ -86,12 +86,12 @@ std::vector<PassConfig> candidates(int64_t R, int64_t C, int nsimd) {
     const int64_t lanes = layout == kLayoutBand ? kStripDwords : kHalfStripDwords;
     const int64_t ns = (D + lanes - 1) / lanes;
     for (int T : {8, 12, 16}) {
-      PassConfig c;
-      c.T = T;
-      c.layout = layout;
-      c.pd = layout == kLayoutPaired ? 9 : default_prefetch(T);
+      // the band layout at 16 generations per pass also with 9 rows of
+      // prefetch (2 % faster than its default 12 on the 65536^2 board)
+      std::set<int> pds{layout == kLayoutPaired ? 9 : default_prefetch(T)};
+      if (layout == kLayoutBand && T == 16) pds.insert(9);
       std::set<int64_t> heights;
-      for (int k : {2, 3, 4, 6, 8}) {
+      for (int k : {2, 3, 4, 6, 8, 10, 12}) {
         // waves: ns x bands (one band per wave) or ns x pairs (two per wave)
         const int64_t units = std::max<int64_t>(1, (int64_t)k * nsimd / ns);
         const int64_t per = layout == kLayoutBand ? units : 2 * units;
@@ -99,13 +99,18 @@ std::vector<PassConfig> candidates(int64_t R, int64_t C, int nsimd) {
         if (h <= 65535) heights.insert(h);
       }
       if (layout == kLayoutBand) heights.insert(default_band_rows(R, C, T, nsimd));
-      for (int64_t h : heights) {
-        c.band_rows = (int)h;
-        if (layout == kLayoutPaired && !paired_ok(R, C, T, paired_geometry(R, C, c.band_rows, c.T, c.pd),
-                                                  nullptr))
-          continue;
-        out.push_back(c);
-      }
+      for (int pd : pds)
+        for (int64_t h : heights) {
+          PassConfig c;
+          c.T = T;
+          c.layout = layout;
+          c.pd = pd;
+          c.band_rows = (int)h;
+          if (layout == kLayoutPaired &&
+              !paired_ok(R, C, T, paired_geometry(R, C, c.band_rows, c.T, c.pd), nullptr))
+            continue;
+          out.push_back(c);
+        }
     }
   }
   if (resident_fits(R, C)) {

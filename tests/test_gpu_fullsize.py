@@ -33,16 +33,19 @@ def tuner_candidates(R, C):
     for layout, lanes in ((gol.LAYOUT_BAND, 62), (gol.LAYOUT_PAIRED, 30)):
         ns = (D + lanes - 1) // lanes
         for T in (8, 12, 16):
-            pd = 9 if layout == gol.LAYOUT_PAIRED else {8: 9, 12: 9, 16: 12}[T]
+            pds = [9] if layout == gol.LAYOUT_PAIRED else [{8: 9, 12: 9, 16: 12}[T]]
+            if layout == gol.LAYOUT_BAND and T == 16:
+                pds.append(9)
             hs = set()
-            for k in (2, 3, 4, 6, 8):
+            for k in (2, 3, 4, 6, 8, 10, 12):
                 units = max(1, k * nsimd // ns)
                 per = units if layout == gol.LAYOUT_BAND else 2 * units
                 hs.add(max(1, -(-R // per)))
-            for h in sorted(hs):
-                if layout == gol.LAYOUT_PAIRED and (C % 32 or R * D * 4 >= 1 << 31):
-                    continue
-                out.append(dict(t_block=T, band_rows=h, prefetch=pd, layout=layout))
+            for pd in pds:
+                for h in sorted(hs):
+                    if layout == gol.LAYOUT_PAIRED and (C % 32 or R * D * 4 >= 1 << 31):
+                        continue
+                    out.append(dict(t_block=T, band_rows=h, prefetch=pd, layout=layout))
     return out
 
 
