@@ -359,7 +359,7 @@ typedef struct {
   double starved_s;        /* host-observed seconds with no chunk queued while boards had
                               generations left (the device waited for the scheduler) */
   double chunk_gap_s;      /* device seconds between one chunk's end and the next one's
-                              start (waiting for uploads, or for the scheduler) */
+                              start, over chunks queued while another was in flight */
 } gol_serve_stats;
 int gol_serve_get_stats(const gol_server* srv, gol_serve_stats* out);
 int gol_serve_destroy(gol_server* srv);

@@ -97,9 +97,11 @@ class Exec {
   virtual int host_free_after(bool compute, void* pinned, size_t cls) = 0;
   virtual bool done(Token t) = 0;
   virtual double seconds(Token chunk) = 0;  // device time of a completed chunk
-  // Device time between the end of the chunk queued before this completed
-  // one and this one's start (0 if unknown).
+  // Device time between the end of the chunk completed before this one and
+  // this one's start (0 if unknown); called once per chunk, in order.
   virtual double gap_before(Token chunk) { (void)chunk; return 0.0; }
+  // No chunk is queued: the next one starts a new run of chunks.
+  virtual void chunks_idle() {}
   virtual void release(Token t) = 0;
   virtual void reap() = 0;
   virtual void sync() = 0;
@@ -123,6 +125,7 @@ class HipExec : public Exec {
       delete c;
     }
     for (hipEvent_t ev : events_) (void)hipEventDestroy(ev);
+    if (ref_) (void)hipEventDestroy(ref_);
     if (compute_) (void)hipStreamDestroy(compute_);
     if (compute2_) (void)hipStreamDestroy(compute2_);
     if (up_) (void)hipStreamDestroy(up_);
@@ -153,6 +156,7 @@ class HipExec : public Exec {
       e = hipExtStreamCreateWithCUMask(&compute2_, (uint32_t)all_cus.size(), all_cus.data());
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&up_, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&down_, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&ref_);
     for (Slot& c : slots_) {
       if (e == hipSuccess) e = hipEventCreate(&c.start);
       if (e == hipSuccess) e = hipEventCreate(&c.end);
@@ -254,7 +258,6 @@ class HipExec : public Exec {
     const size_t oi = os + al(hp.segs.size() * sizeof(Segment));
     const size_t mb = oi + al(hp.items.size() * sizeof(WaveItem));
     Slot& c = slots_[next_slot_];
-    c.index = next_slot_;
     next_slot_ = (next_slot_ + 1) % kSlots;
     hipError_t e = hipSuccess;
     if (c.busy) e = hipEventSynchronize(c.end);  // not reached while two chunks at most are queued
@@ -282,7 +285,12 @@ class HipExec : public Exec {
     memcpy(pin, bd.data(), bd.size() * sizeof(BoardDesc));
     memcpy(pin + os, hp.segs.data(), hp.segs.size() * sizeof(Segment));
     memcpy(pin + oi, hp.items.data(), hp.items.size() * sizeof(WaveItem));
-    e = hipEventRecord(c.start, compute_);
+    if (e == hipSuccess && !ref_valid_) {
+      e = hipEventRecord(ref_, compute_);
+      ref_valid_ = e == hipSuccess;
+      prev_end_ = -1.0;
+    }
+    if (e == hipSuccess) e = hipEventRecord(c.start, compute_);
     if (e == hipSuccess) e = hipMemcpyAsync(c.meta, pin, mb, hipMemcpyHostToDevice, compute_);
     const BoardDesc* d_b = (const BoardDesc*)c.meta;
     const Segment* d_s = (const Segment*)((char*)c.meta + os);
@@ -291,7 +299,6 @@ class HipExec : public Exec {
     if (e == hipSuccess) e = hipEventRecord(c.end, compute_);
     if (e != hipSuccess) return hip_error(e, "server: chunk launch");
     c.busy = true;
-    c.seq = ++seq_;
     *done = &c;
     return GOL_OK;
   }
@@ -337,22 +344,25 @@ class HipExec : public Exec {
   // The slot before a chunk's in the ring held the chunk queued before it
   // (its events are reused only by the chunk after next, which is queued
   // after this one completes).
+  // Both ends of each chunk are timed against one reference event recorded
+  // before the first chunk of a run of chunks (consecutive chunks' own
+  // events do not always give an elapsed time to each other).
   double gap_before(Token t) override {
     const Tagged* g = (const Tagged*)t;
-    if (g->kind != 0) return 0.0;
+    if (g->kind != 0 || !ref_valid_) return 0.0;
     const Slot* c = (const Slot*)t;
-    const Slot& p = slots_[(c->index + kSlots - 1) % kSlots];
-    if (p.seq + 1 != c->seq) return 0.0;
-    // both intervals from the earlier chunk's start event (the start-to-end
-    // pair is the one seconds() reads); a failed query leaves no error behind
-    float to_start = 0.f, to_end = 0.f;
-    if (hipEventElapsedTime(&to_start, p.start, c->start) != hipSuccess ||
-        hipEventElapsedTime(&to_end, p.start, p.end) != hipSuccess) {
+    float a = 0.f, b = 0.f;
+    if (hipEventElapsedTime(&a, ref_, c->start) != hipSuccess ||
+        hipEventElapsedTime(&b, ref_, c->end) != hipSuccess) {
       (void)hipGetLastError();
+      prev_end_ = -1.0;
       return 0.0;
     }
-    return to_start > to_end ? (to_start - to_end) * 1e-3 : 0.0;
+    const double gap = prev_end_ >= 0.0 ? a * 1e-3 - prev_end_ : 0.0;
+    prev_end_ = b * 1e-3;
+    return gap > 0.0 ? gap : 0.0;
   }
+  void chunks_idle() override { ref_valid_ = false; }
   void release(Token t) override {
     Tagged* g = (Tagged*)t;
     if (!g) return;
@@ -395,8 +405,6 @@ class HipExec : public Exec {
     void* meta = nullptr;
     size_t meta_bytes = 0;
     bool busy = false;
-    int index = 0;     // position in the ring
-    uint64_t seq = 0;  // order in which chunks were queued (1, 2, ...)
   };
   struct Copy : Tagged {
     hipEvent_t end = nullptr;  // kept with the record for its next use
@@ -461,7 +469,9 @@ class HipExec : public Exec {
   hipStream_t compute2_ = nullptr;  // the late group of each chunk's schedule
   Slot slots_[kSlots];
   int next_slot_ = 0;
-  uint64_t seq_ = 0;
+  hipEvent_t ref_ = nullptr;  // timing reference of the current run of chunks
+  bool ref_valid_ = false;
+  double prev_end_ = -1.0;    // end of the last completed chunk, seconds after ref_
   std::vector<Copy*> copies_free_;
   std::vector<hipEvent_t> events_;  // free events
   std::vector<Pending> pending_;    // touched by the scheduler thread under the server lock
@@ -716,6 +726,7 @@ static void reap(Server& S) {
     S.exec->release(S.chunks.front());
     S.chunks.pop_front();
     S.chunk_cu.pop_front();
+    if (S.chunks.empty()) S.exec->chunks_idle();
     if (S.chunks.empty() && S.t_starved < 0.0) {
       bool work = !S.queue.empty();
       for (size_t i = 0; !work && i < S.resident.size(); ++i) {
