@@ -135,15 +135,18 @@ class HipExec : public Exec {
     int prev = 0;
     (void)hipGetDevice(&prev);
     hipError_t e = hipSetDevice(dev_);
-    // The two compute streams get hardware queues of their own: streams
-    // created plainly share the runtime's few queues (GPU_MAX_HW_QUEUES) with
-    // every other stream of the process, so which queues they land on depends
-    // on the streams created and destroyed before; a compute stream sharing a
+    // All four streams get hardware queues of their own: streams created
+    // plainly share the runtime's few queues (GPU_MAX_HW_QUEUES) with every
+    // other stream of the process, so which queues they land on depends on
+    // the streams created and destroyed before.  A compute stream sharing a
     // queue with the download stream waits behind its copies and the device
     // idles between chunks (measured: 0.15 s of gaps instead of 0.02 over a
     // stream of about 0.8 s, 7 % less throughput at 0.7 of capacity and 18 %
-    // at 0.9).  A stream with a CU mask (here every CU, so it runs like any
-    // other) has a queue of its own.
+    // at 0.9); the upload stream sharing one with the download stream, whose
+    // copies wait for chunks, makes single upload calls hold up the scheduler
+    // thread for up to 40 ms (measured on a second server of one process: a
+    // saturated burst 0.8 of the first server's rate).  A stream with a CU
+    // mask (here every CU, so it runs like any other) has a queue of its own.
     std::vector<uint32_t> all_cus;
     int ncu = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_);
@@ -154,8 +157,10 @@ class HipExec : public Exec {
     }
     if (e == hipSuccess)
       e = hipExtStreamCreateWithCUMask(&compute2_, (uint32_t)all_cus.size(), all_cus.data());
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&up_, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&down_, hipStreamNonBlocking);
+    if (e == hipSuccess)
+      e = hipExtStreamCreateWithCUMask(&up_, (uint32_t)all_cus.size(), all_cus.data());
+    if (e == hipSuccess)
+      e = hipExtStreamCreateWithCUMask(&down_, (uint32_t)all_cus.size(), all_cus.data());
     if (e == hipSuccess) e = hipEventCreate(&ref_);
     for (Slot& c : slots_) {
       if (e == hipSuccess) e = hipEventCreate(&c.start);
