@@ -294,7 +294,12 @@ int gol_plan_destroy(gol_plan* plan);
  * tick, finished boards are copied back and leave.
  */
 typedef struct gol_serve_config {
-  uint64_t hbm_budget_bytes;   /* device bytes for resident boards */
+  uint64_t hbm_budget_bytes;   /* device bytes for resident boards: two buffers per board,
+                                  each rounded up to a size class at most 25 % above the
+                                  board's packed bytes (classes a quarter power of two
+                                  apart, at least 4 KiB); buffers of retired boards stay
+                                  cached for the next board of their class while the
+                                  buffers held, in use or cached, fit this budget */
   int32_t chunk_generations;   /* generations per tick (>= 1), or 0: automatic -- each
                                   tick runs the whole passes that take the resident boards
                                   about 3 ms of device time at the rate measured on earlier

@@ -64,7 +64,9 @@ def test_serve_budget_forces_queueing():
     R, C, G = 200, 640, 30
     bytes_per = 2 * R * gol.words_per_row(C) * 8
     boards = [rand_bytes(3, i, R, C, 0.4) for i in range(5)]
-    with gol.Server(hbm_budget_bytes=bytes_per + 100, chunk_generations=8) as srv:
+    # one board's buffers, rounded up to their size class (at most 25 % more),
+    # fit; two boards' do not
+    with gol.Server(hbm_budget_bytes=bytes_per * 3 // 2, chunk_generations=8) as srv:
         tickets = [srv.submit(oracle.pack(b), R, C, G) for b in boards]
         infos = []
         for b, t in zip(boards, tickets):
