@@ -77,6 +77,41 @@ def test_serve_budget_forces_queueing():
         assert b.admit_s >= a.done_s - 1e-3 or b.admit_s >= a.admit_s  # admitted one by one
 
 
+def test_serve_reuses_and_evicts_buffers_under_budget():
+    """Waves of boards of a few sizes under a budget that holds only a few at
+    a time: buffers of retired and cancelled boards are reused by later
+    boards of their size class and handed back to the device pool when
+    another class needs the room.  Every result equals the oracle and the
+    resident bytes stay within the budget."""
+    # packed bytes per buffer: 32768, 32000 (the same class), 76800, 188000, 640
+    shapes = [(256, 1024), (250, 1000), (300, 2000), (500, 3000), (40, 70)]
+    budget = 3 * 2 * 196608  # three of the largest class (188000 rounded up)
+    rng = np.random.default_rng(11)
+    reqs = []
+    for i in range(30):
+        R, C = shapes[int(rng.integers(0, len(shapes)))]
+        reqs.append((rand_bytes(11, i, R, C, float(rng.uniform(0.2, 0.5))), R, C,
+                     int(rng.integers(0, 40))))
+    with gol.Server(hbm_budget_bytes=budget, chunk_generations=8) as srv:
+        tickets = [srv.submit(oracle.pack(b), R, C, G) for b, R, C, G in reqs]
+        cancelled = {3, 17}
+        for i in cancelled:
+            srv.cancel(tickets[i])
+        for i, ((b, R, C, G), t) in enumerate(zip(reqs, tickets)):
+            out = np.zeros((R, gol.words_per_row(C)), np.uint64)
+            if i in cancelled:
+                try:  # it may have finished before the cancel reached it
+                    srv.wait(t, out)
+                except gol.GolError as e:
+                    assert e.code == gol.GOL_ECANCELED
+                    continue
+            else:
+                srv.wait(t, out)
+            assert np.array_equal(out, expect_words(b, G)), (i, R, C, G)
+        st = srv.stats()
+    assert 0 < st["peak_resident_bytes"] <= budget
+
+
 def test_serve_oversize_and_bad_tickets():
     with gol.Server(hbm_budget_bytes=1 << 20, chunk_generations=8) as srv:
         big = np.zeros((2048, 64), np.uint64)  # needs 2 x 1 MiB > budget
