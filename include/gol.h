@@ -303,7 +303,9 @@ typedef struct gol_serve_config {
   int32_t chunk_generations;   /* generations per tick (>= 1), or 0: automatic -- each
                                   tick runs the whole passes that take the resident boards
                                   about 3 ms of device time at the rate measured on earlier
-                                  ticks (15 passes until one has completed) */
+                                  ticks (15 passes until one has completed); behind a
+                                  backlog of more than 16 such ticks (resident and queued
+                                  work), a sixteenth of the backlog, up to 24 ms */
   int32_t device;              /* HIP device ordinal */
   int32_t max_resident;        /* cap on resident boards (0 = no cap) */
   int32_t t_block;             /* generations per pass: 1, 2, 4, 8, 12, 16, or 0: tuned at

@@ -828,22 +828,39 @@ constexpr double kAdmitSlice = 0.001;
 
 // Device time a chunk of an automatic length aims at: long enough that its
 // launches and host work are small beside it, short enough that a request
-// arriving meanwhile waits little before it joins.
+// arriving meanwhile waits little before it joins.  Behind a deep backlog
+// (the work resident and queued would take more than 16 such chunks) the
+// chunk aims at a sixteenth of that backlog, up to kChunkTargetMaxSeconds:
+// every request then waits mostly for the backlog anyway, and fewer chunks
+// end in fewer joins (measured with all 4096 requests of the served
+// workload at once: 0.88 of the batched capacity against 0.85 at 3 ms,
+// with the Poisson streams' rates and latencies unchanged).
 constexpr double kChunkTargetSeconds = 0.003;
+constexpr double kChunkTargetMaxSeconds = 0.024;
+constexpr double kChunkBacklogShare = 1.0 / 16.0;
 // Generations of the first chunks of an automatic length (no rate measured yet).
 constexpr int64_t kChunkFirstPasses = 15;
 constexpr int64_t kChunkMaxPasses = 256;
 
 // Generations every board advances in the next chunk (at most; fewer if it
 // finishes): the configured count, or (chunk_generations 0) as many whole
-// passes as the resident cells take about kChunkTargetSeconds of device time
-// at the rate measured on earlier chunks.
+// passes as the resident cells take the target device time (above) at the
+// rate measured on earlier chunks.
 static int64_t chunk_generations(const Server& S, const std::vector<Request*>& act) {
   if (S.cfg.chunk_generations > 0) return S.cfg.chunk_generations;
   if (S.rate <= 0.0) return kChunkFirstPasses * S.T;
-  double cells = 0.0;
-  for (const Request* r : act) cells += (double)r->rows * (double)r->cols;
-  const double g = kChunkTargetSeconds * S.rate / std::max(cells, 1.0);
+  double cells = 0.0, backlog = 0.0;  // cells in the chunk; cell updates left
+  for (const Request* r : act) {
+    cells += (double)r->rows * (double)r->cols;
+    backlog += (double)r->rows * (double)r->cols * (double)(r->gens - r->queued_gens);
+  }
+  for (uint64_t t : S.queue) {
+    const Request& q = *S.reqs.at(t);
+    backlog += (double)q.rows * (double)q.cols * (double)q.gens;
+  }
+  const double target = std::min(kChunkTargetMaxSeconds,
+                                 std::max(kChunkTargetSeconds, kChunkBacklogShare * backlog / S.rate));
+  const double g = target * S.rate / std::max(cells, 1.0);
   const int64_t passes = std::min<int64_t>(kChunkMaxPasses,
                                            std::max<int64_t>(1, (int64_t)std::ceil(g / S.T)));
   return passes * S.T;
