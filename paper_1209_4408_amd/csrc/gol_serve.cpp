@@ -20,7 +20,8 @@
 //
 // The scheduler talks to the device through an executor.  HipExec is the
 // real one (compute streams, upload and download streams, events,
-// stream-ordered memory, the library's pinned staging pool).
+// stream-ordered memory with released board buffers cached by size class,
+// the library's pinned staging pool).
 // HostExec keeps boards in host memory and completes every operation at once;
 // it exists so the scheduling policy (admission order, budget, chunking,
 // buffer bookkeeping, retirement, cancellation, failures) and each chunk's
@@ -466,7 +467,7 @@ class HipExec : public Exec {
     return c;
   }
   // Waits on the host for an event: then the pinned block returns to the
-  // pool, or the device block is freed on the upload stream.
+  // pool, or the device block is released (release_block: cached or freed).
   struct Pending {
     hipEvent_t ev;
     void* pinned;
