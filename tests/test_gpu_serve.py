@@ -235,3 +235,29 @@ def test_serve_automatic_chunks_match_oracle(T):
     assert st["t_block"] == (T or st["t_block"]) and st["t_block"] in (8, 12, 16)
     assert st["last_chunk_generations"] % st["t_block"] == 0
     assert st["last_band_rows"] >= 16
+
+
+def test_serve_deep_backlog_equals_alone():
+    """All requests at once with enough work (4.8e12 cell updates) that the
+    automatic chunk length follows the backlog, chunks longer than its 3 ms
+    floor: every result equals the board run alone by step_packed (itself
+    checked against the oracle)."""
+    import torch
+    n, R, C, G = 48, 4096, 4096, 6000
+    dev = torch.device("cuda:0")
+    boards = [seeded_inputs.board_packed_device(1209, 500 + i, R, C, 0.4, gol.empty_packed(R, C, dev))
+              for i in range(n)]
+    host = [from_dev(d) for d in boards]
+    say("serve deep backlog", n, R, C, G)
+    with gol.Server(hbm_budget_bytes=8 << 30, chunk_generations=0) as srv:
+        tickets = [srv.submit(w, R, C, G) for w in host]
+        outs = []
+        for w, t in zip(host, tickets):
+            out = np.zeros_like(w)
+            srv.wait(t, out)
+            outs.append(out)
+        st = srv.stats()
+    assert st["retired"] == n
+    for i, (d, out) in enumerate(zip(boards, outs)):
+        say("alone", i)
+        assert np.array_equal(out, from_dev(gol.step_packed(d, R, C, G))), i
